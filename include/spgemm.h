@@ -1,0 +1,199 @@
+/*
+ * spgemm.h -- C ABI of libspgemm, a general sparse matrix-matrix
+ * multiplication C = A*B on CSR matrices for AMD Instinct MI355X (gfx950).
+ *
+ * The method follows W. Liu and B. Vinter, "A Framework for General Sparse
+ * Matrix-Matrix Multiplication on GPUs and Heterogeneous Processors"
+ * (J. Parallel Distrib. Comput., extended version of IPDPS'14):
+ *   stage 1  per-row upper bound u_i of nnz(c_i*) (Algorithm 2),
+ *   stage 2  binning of the rows by u_i into 38 bins (Algorithm 3),
+ *   stage 3  hybrid allocation of the temporary matrix C~ (u_i entries for
+ *            short rows, 256 for long rows, progressive 2x growth beyond)
+ *            and the per-bin insert kernels (Section 3.1, "the third stage"),
+ *   stage 4  arranging data: row pointers of C from the row sizes, then a
+ *            copy of C~ into C (Section 3.1, "the fourth stage").
+ * The output nnz is not known in advance (Section 3.1): analyze runs stages
+ * 1-2 and sizes C~, compute runs stages 3-4 and allocates C through the
+ * caller's allocator.
+ *
+ * Conventions for every entry point:
+ *  - All matrix arrays are DEVICE pointers on the current HIP device.  Index
+ *    arrays are int32; value arrays are binary32 or binary64 (spgemm_dtype).
+ *    Inputs must have row_ptr[0] = 0, non-decreasing row_ptr and strictly
+ *    increasing column indices inside each row (the paper assumes sorted
+ *    columns, Section 2.3 footnote); with options.validate != 0 this is
+ *    checked on the device and violations return SPGEMM_EINVAL.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *    All device work is ordered on that stream.
+ *  - Return value: SPGEMM_OK (0) or a negative spgemm_status.  On error no
+ *    caller-owned memory is leaked or left half-written, and no C++
+ *    exception crosses the boundary.
+ *  - Memory: the library obtains device memory only through the caller's
+ *    spgemm_alloc_fn / spgemm_free_fn (NULL pointers select the HIP
+ *    stream-ordered allocator).  Inputs stay owned by the caller.  Plans own
+ *    their scratch and release it in spgemm_plan_destroy.  Output arrays of C
+ *    are allocated with alloc_fn and then belong to the caller.
+ */
+#ifndef SPGEMM_H
+#define SPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPGEMM_OK = 0,
+  SPGEMM_EINVAL = -1,    /* bad argument, shape or dtype mismatch, invalid CSR */
+  SPGEMM_ENOMEM = -2,    /* alloc_fn returned NULL                              */
+  SPGEMM_EOVERFLOW = -3, /* nnz(C) or another count does not fit the index type */
+  SPGEMM_EHIP = -4,      /* HIP runtime error (spgemm_last_error has details)   */
+  SPGEMM_ESTATE = -5     /* plan used with matrices other than those analyzed   */
+} spgemm_status;
+
+typedef enum { SPGEMM_F32 = 0, SPGEMM_F64 = 1 } spgemm_dtype;
+
+/* A borrowed CSR view (the library never frees it).  rows x cols, nnz
+ * entries: row_ptr[rows+1], col_idx[nnz], val[nnz] of `dtype`. */
+typedef struct {
+  int64_t rows, cols, nnz;
+  const int32_t *row_ptr;
+  const int32_t *col_idx;
+  const void *val;
+  int32_t dtype;
+} spgemm_csr;
+
+/* An output CSR.  The three arrays are allocated by the library through the
+ * caller's alloc_fn and owned by the caller afterwards. */
+typedef struct {
+  int64_t rows, cols, nnz;
+  int32_t *row_ptr;
+  int32_t *col_idx;
+  void *val;
+  int32_t dtype;
+} spgemm_csr_out;
+
+/* Device allocator: return `bytes` of device memory usable in stream order on
+ * `stream`, or NULL on failure.  free_fn releases a pointer from alloc_fn. */
+typedef void *(*spgemm_alloc_fn)(size_t bytes, void *ctx, void *stream);
+typedef void (*spgemm_free_fn)(void *ptr, void *ctx, void *stream);
+
+/* Tuning knobs.  spgemm_default_options() gives the paper's settings
+ * (Algorithm 3 thresholds, 256-entry long-row slot, 2x growth).  None of
+ * them changes the structure of C; values are identical for every setting
+ * except for long rows whose work is split or whose result spills out of the
+ * on-chip level-1 sequence (summation order differs, within rounding). */
+typedef struct {
+  /* upper row sizes of: the single-size bins (group 3, default 32), then the
+   * four range bins of group 4 (defaults 64, 128, 256, 512).  Rows above the
+   * last edge form bin 37 (group 5).  Strictly increasing, edge[0] in
+   * [1, 32], edge[4] <= 2048. */
+  int32_t bin_edges[5];
+  int32_t long_slot;    /* C~ entries reserved per long row (default 256)     */
+  int32_t l1_cap;       /* level-1 (LDS) sequence entries of the long-row
+                           kernel, 0 = automatic                              */
+  int64_t seg;          /* max products per long-row work item (rows with
+                           more are split across work-groups); 0 = automatic,
+                           < 0 = never split                                  */
+  int64_t pool_entries; /* initial long-row pool size in entries, 0 = auto   */
+  int32_t validate;     /* nonzero: check the input CSR arrays on the device  */
+  int32_t timing;       /* nonzero: record per-stage times into spgemm_info   */
+} spgemm_options;
+
+#define SPGEMM_NBINS 38
+#define SPGEMM_NSTAGES 8
+
+/* Per-stage timer slots of spgemm_info.stage_ms (options.timing != 0). */
+enum {
+  SPGEMM_T_UPPER = 0,   /* stage 1: upper bounds and scan                    */
+  SPGEMM_T_BIN = 1,     /* stage 2: binning, C~ offsets                      */
+  SPGEMM_T_TINY = 2,    /* stage 3: rows with u <= edge[0]                   */
+  SPGEMM_T_MEDIUM = 3,  /* stage 3: rows in the four range bins              */
+  SPGEMM_T_LONG = 4,    /* stage 3: long rows (all relaunch rounds)          */
+  SPGEMM_T_SCAN = 5,    /* stage 4: row pointers of C                        */
+  SPGEMM_T_COPY = 6,    /* stage 4: copy C~ into C                           */
+  SPGEMM_T_BACKWARD = 7 /* backward kernels                                  */
+};
+
+typedef struct {
+  int64_t m, k, n;
+  int64_t flops;        /* 2 * sum(u_i) (Table 2 caption)                     */
+  int64_t nnz_hat;      /* sum(u_i) = nnz of the expanded matrix             */
+  int64_t nnz_tilde;    /* sum of C~ row sizes (Algorithm 3)                 */
+  int64_t nnz_c;        /* nnz(C), after compute                             */
+  int64_t max_u;
+  int64_t bin_count[SPGEMM_NBINS];
+  int64_t long_items;   /* long-row work items after splitting               */
+  int64_t bytes_scratch;/* device scratch held by the plan                   */
+  int64_t pool_entries; /* long-row pool capacity at the end of compute      */
+  int64_t pool_used;    /* entries taken from the pool                       */
+  int32_t realloc_rounds; /* pool exhaustions handled by relaunching         */
+  int32_t reserved;
+  float stage_ms[SPGEMM_NSTAGES];
+  float long_kernel_ms; /* summed duration of the long-row kernel launches   */
+  int32_t long_launches;
+} spgemm_info;
+
+typedef struct spgemm_plan_s *spgemm_plan;
+
+/* Fill `opt` with the defaults described above. */
+void spgemm_default_options(spgemm_options *opt);
+
+/* Human-readable text of a status code (static storage). */
+const char *spgemm_strerror(int code);
+
+/* Detail of the last SPGEMM_EHIP / SPGEMM_EINVAL raised in this thread. */
+const char *spgemm_last_error(void);
+
+/*
+ * Stages 1-2 (Algorithms 2 and 3) plus the sizing of C~ (hybrid allocation,
+ * Section 3.1).  Computes u_i for every row of C, bins the rows and reserves
+ * the plan's scratch; synchronizes `stream` once to read back a small
+ * summary (sums, bin counts).  A: m x k, B: k x n, same dtype.  The plan
+ * remembers the pointers and sizes of A's and B's index arrays; later calls
+ * must pass the same matrices (values may change).  `opt` may be NULL
+ * (defaults); `info` may be NULL.  On success *plan is a new plan.
+ */
+int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B, const spgemm_options *opt,
+                   spgemm_alloc_fn alloc_fn, spgemm_free_fn free_fn, void *ctx,
+                   void *stream, spgemm_plan *plan, spgemm_info *info);
+
+/*
+ * Stages 3-4: computes every row of C into C~ (bin groups 1-5 with their
+ * own kernels), sums the row sizes into C's row pointers, allocates C's
+ * column and value arrays (exactly nnz(C) entries) with the plan's allocator
+ * and copies C~ into C.  Synchronizes `stream` once to read nnz(C), plus once
+ * more per exhaustion of the long-row pool (the pool then grows 2x and the
+ * affected long rows resume from their checkpoints).  C receives rows = m,
+ * cols = n, nnz, three owned arrays and A's dtype.  Entries of every row are
+ * in ascending column order without duplicates; structural products that
+ * cancel are kept.
+ */
+int spgemm_compute(spgemm_plan plan, const spgemm_csr *A, const spgemm_csr *B,
+                   spgemm_csr_out *C, void *stream, spgemm_info *info);
+
+/*
+ * Gradient of L = <dC, A*B> for the values of A and B on their fixed
+ * patterns: dA_ij = sum_k dC_ik b_jk over the stored b_jk (= (dC B^T) on
+ * S(A)), dB_jk = sum_i a_ij dC_ik over the stored a_ij (= (A^T dC) on S(B)).
+ * `C` must be the result of spgemm_compute for this plan, with C->val holding
+ * dC (same pattern as C, A's dtype).  dA_val (nnz(A) entries) or dB_val
+ * (nnz(B) entries) may be NULL to skip them.  Device pointers.  Fully
+ * asynchronous on `stream`.
+ */
+int spgemm_backward(spgemm_plan plan, const spgemm_csr *A, const spgemm_csr *B,
+                    const spgemm_csr *C, void *dA_val, void *dB_val, void *stream);
+
+/* Fill `info` with the plan's latest statistics. */
+int spgemm_plan_info(spgemm_plan plan, spgemm_info *info);
+
+/* Release the plan and its scratch (ordered on the plan's last stream). */
+int spgemm_plan_destroy(spgemm_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPGEMM_H */

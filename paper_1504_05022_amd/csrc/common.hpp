@@ -1,0 +1,237 @@
+// Device building blocks shared by the SpGEMM kernels: wavefront and
+// work-group scans, cross-lane exchange, and bitonic sorting networks laid
+// out for 64-wide wavefronts (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DEVI __device__ __forceinline__
+
+namespace spg {
+
+constexpr int WAVE = 64;
+
+DEVI int lane() { return static_cast<int>(__lane_id()); }
+
+// ---------------------------------------------------------------- shuffles
+
+DEVI uint32_t shfl_xor_u32(uint32_t v, int m) {
+  return static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), m, WAVE));
+}
+DEVI uint64_t shfl_xor_u64(uint64_t v, int m) {
+  return static_cast<uint64_t>(__shfl_xor(static_cast<long long>(v), m, WAVE));
+}
+template <typename K> DEVI K shfl_xor_key(K v, int m);
+template <> DEVI uint32_t shfl_xor_key<uint32_t>(uint32_t v, int m) { return shfl_xor_u32(v, m); }
+template <> DEVI uint64_t shfl_xor_key<uint64_t>(uint64_t v, int m) { return shfl_xor_u64(v, m); }
+
+template <typename K> DEVI K shfl_up_key(K v, int d);
+template <> DEVI uint32_t shfl_up_key<uint32_t>(uint32_t v, int d) {
+  return static_cast<uint32_t>(__shfl_up(static_cast<int>(v), d, WAVE));
+}
+template <> DEVI uint64_t shfl_up_key<uint64_t>(uint64_t v, int d) {
+  return static_cast<uint64_t>(__shfl_up(static_cast<long long>(v), d, WAVE));
+}
+
+// ------------------------------------------------------------- group scans
+// Scans over aligned groups of G consecutive lanes (G a power of two <= 64).
+
+template <int G, typename V> DEVI V group_incl_sum(V x) {
+  const int lg = lane() & (G - 1);
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    V y = __shfl_up(x, o, WAVE);
+    if (lg >= o) x += y;
+  }
+  return x;
+}
+
+template <int G> DEVI int group_incl_max(int x) {
+  const int lg = lane() & (G - 1);
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    int y = __shfl_up(x, o, WAVE);
+    if (lg >= o) x = max(x, y);
+  }
+  return x;
+}
+
+// Value held by the last lane of the group.
+template <int G, typename V> DEVI V group_last(V x) {
+  return __shfl(x, (lane() & ~(G - 1)) + G - 1, WAVE);
+}
+
+// Work-group exclusive sum of one value per thread.  `smem` holds NT/64 + 1
+// entries.  Returns the exclusive prefix; `total` receives the block sum.
+// Contains barriers: every thread of the block must call it.
+template <int NT, typename V> DEVI V block_excl_sum(V x, V *smem, V &total) {
+  constexpr int NW = NT / WAVE;
+  V inc = group_incl_sum<WAVE>(x);
+  const int w = threadIdx.x / WAVE;
+  if (lane() == WAVE - 1) smem[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    V run = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      V t = smem[i];
+      smem[i] = run;
+      run += t;
+    }
+    smem[NW] = run;
+  }
+  __syncthreads();
+  V res = smem[w] + inc - x;
+  total = smem[NW];
+  __syncthreads();
+  return res;
+}
+
+// Work-group inclusive max of one int per thread (same contract).
+template <int NT> DEVI int block_incl_max(int x, int *smem) {
+  constexpr int NW = NT / WAVE;
+  int inc = group_incl_max<WAVE>(x);
+  const int w = threadIdx.x / WAVE;
+  if (lane() == WAVE - 1) smem[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = -1;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      int t = smem[i];
+      smem[i] = run;
+      run = max(run, t);
+    }
+  }
+  __syncthreads();
+  int res = max(smem[w], inc);
+  __syncthreads();
+  return res;
+}
+
+// Work-group exclusive max of one int per thread: max over threads < t, or
+// -1 for thread 0.  `smem` holds NT/64 ints.  Contains barriers.
+template <int NT> DEVI int block_excl_max(int x, int *smem) {
+  constexpr int NW = NT / WAVE;
+  const int inc = group_incl_max<WAVE>(x);
+  const int w = threadIdx.x / WAVE;
+  if (lane() == WAVE - 1) smem[w] = inc;
+  int prev = __shfl_up(inc, 1, WAVE);
+  if (lane() == 0) prev = -1;
+  __syncthreads();
+  int before = -1;
+#pragma unroll
+  for (int i = 0; i < NW; ++i)
+    if (i < w) before = max(before, smem[i]);
+  __syncthreads();
+  return max(before, prev);
+}
+
+// ------------------------------------------------------------ bitonic sort
+// Keys are held K per lane in "blocked" order: lane position p (0..G-1 in its
+// group, or the thread index for the work-group version) holds elements
+// p*K .. p*K+K-1.  Sorting is ascending.  Strides below K are exchanged in
+// registers, strides up to K*G through cross-lane shuffles.
+
+template <typename Key> DEVI void cas_pair(Key &a, Key &b, bool asc) {
+  Key lo = a < b ? a : b;
+  Key hi = a < b ? b : a;
+  a = asc ? lo : hi;
+  b = asc ? hi : lo;
+}
+
+// One bitonic stage (size, stride) on register-resident keys, strides < K.
+template <int K, typename Key>
+DEVI void stage_regs(Key (&k)[K], int pos, int size, int stride) {
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int p = kk ^ stride;
+    if (p > kk) {
+      const int i = pos * K + kk;
+      cas_pair(k[kk], k[p], (i & size) == 0);
+    }
+  }
+}
+
+// One stage with stride >= K: partner lane differs by stride/K.
+template <int K, typename Key>
+DEVI void stage_lanes(Key (&k)[K], int pos, int size, int stride) {
+  const int pm = stride / K;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int i = pos * K + kk;
+    Key other = shfl_xor_key<Key>(k[kk], pm);
+    const bool asc = (i & size) == 0;
+    const bool lower = (i & stride) == 0;
+    const bool take_min = (asc == lower);
+    Key mn = k[kk] < other ? k[kk] : other;
+    Key mx = k[kk] < other ? other : k[kk];
+    k[kk] = take_min ? mn : mx;
+  }
+}
+
+// Sort G*K keys held by an aligned group of G lanes (G <= 64).
+template <int G, int K, typename Key> DEVI void group_bitonic_sort(Key (&k)[K]) {
+  constexpr int N = G * K;
+  const int pos = lane() & (G - 1);
+#pragma unroll
+  for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride < K)
+        stage_regs<K, Key>(k, pos, size, stride);
+      else
+        stage_lanes<K, Key>(k, pos, size, stride);
+    }
+  }
+}
+
+// Sort NT*K keys held by a work-group of NT threads.  Strides that cross
+// wavefronts go through `lds` (NT*K keys, layout [kk][thread] so that the
+// exchange is bank-conflict free).  Contains barriers.
+template <int NT, int K, typename Key> DEVI void block_bitonic_sort(Key (&k)[K], Key *lds) {
+  constexpr int N = NT * K;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride < K) {
+        stage_regs<K, Key>(k, t, size, stride);
+      } else if (stride < K * WAVE) {
+        stage_lanes<K, Key>(k, t, size, stride);
+      } else {
+        const int pt = t ^ (stride / K);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) lds[kk * NT + t] = k[kk];
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) {
+          const int i = t * K + kk;
+          Key other = lds[kk * NT + pt];
+          const bool asc = (i & size) == 0;
+          const bool lower = (i & stride) == 0;
+          const bool take_min = (asc == lower);
+          Key mn = k[kk] < other ? k[kk] : other;
+          Key mx = k[kk] < other ? other : k[kk];
+          k[kk] = take_min ? mn : mx;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T> struct KeyMax;
+template <> struct KeyMax<uint32_t> { static constexpr uint32_t v = 0xffffffffu; };
+template <> struct KeyMax<uint64_t> { static constexpr uint64_t v = 0xffffffffffffffffull; };
+
+template <int B> struct Log2 { static constexpr int v = 1 + Log2<B / 2>::v; };
+template <> struct Log2<1> { static constexpr int v = 0; };
+
+// Values are summed without fused multiply-add (the library is compiled with
+// -ffp-contract=off), products first rounded, then added in sequence order.
+
+}  // namespace spg

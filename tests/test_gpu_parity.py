@@ -1,0 +1,238 @@
+"""Parity of the HIP path (through the C ABI) with the oracle.
+
+Structure (row_ptr, col_idx) must match bit for bit; values within the
+componentwise bound |c - c*| <= tol * (|A||B|)_ik with tol = 1e-12 (binary64)
+and 1e-5 (binary32).  Rows that are neither split nor spilled are summed in
+the oracle's order, so their values must match exactly; the tests check
+exact equality wherever that holds.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = {np.dtype(np.float64): 1e-12, np.dtype(np.float32): 1e-5}
+
+
+def _run(A, B, **opts):
+    import torch
+    from paper_1504_05022_amd import CsrMatrix, Plan
+    dA = CsrMatrix.from_host(A)
+    dB = dA if B is A else CsrMatrix.from_host(B)
+    plan = Plan(dA, dB, **opts)
+    C = plan.compute()
+    torch.cuda.synchronize()
+    info = plan.info
+    plan.close()
+    return C, info
+
+
+def check(A, B, exact=True, **opts):
+    """Run the GPU path and compare with the oracle.  Returns (C host tuple, info)."""
+    print("case: A %dx%d nnz %d, B %dx%d nnz %d, %s, opts %s" %
+          (A.rows, A.cols, A.nnz, B.rows, B.cols, B.nnz, A.val.dtype, opts), flush=True)
+    C, info = _run(A, B, **opts)
+    _, _, rp, ci, v = C.to_host()
+    ref = oracle.spgemm(A.astype(np.float64).as_tuple(), B.astype(np.float64).as_tuple())
+    assert np.array_equal(rp.astype(np.int64), ref.row_ptr), "row_ptr differs"
+    assert np.array_equal(ci, ref.col_idx), "col_idx differs"
+    assert info.nnz_c == ref.nnz
+    assert info.flops == ref.flops
+    err, rel = oracle.value_error(v, ref)
+    print("  nnz(C) %d, flops %d, max scaled err %.3g, max rel err %.3g" %
+          (ref.nnz, ref.flops, err, rel), flush=True)
+    assert err <= TOL[np.dtype(A.val.dtype)]
+    if exact:
+        if A.val.dtype == np.float64:
+            assert np.array_equal(v, ref.val), "binary64 values differ from sequential sums"
+        else:
+            r32 = oracle.spgemm(A.as_tuple(), B.as_tuple(), acc32=True)
+            assert np.array_equal(v, r32.val), "binary32 values differ from sequential sums"
+    return (rp, ci, v), info
+
+
+EDGE_U = [0, 1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 32, 33, 63, 64, 65, 127, 128, 129, 255,
+          256, 257, 511, 512, 513, 1000, 1023, 1024, 1025, 2048, 4097]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("col_range", [None, 40, 700])
+def test_bin_edges(dtype, col_range):
+    targets = [t for t in EDGE_U if col_range is None or t <= 16 * 1024]
+    A, B = S.crafted_rows(targets * 3, col_range=col_range, empty_refs=2, dtype=dtype)
+    _, info = check(A, B)
+    b, _, _ = oracle.bins(np.array(targets * 3))
+    assert list(info.bin_count) == np.bincount(b, minlength=38).tolist()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_long_rows_that_spill(dtype):
+    """Results longer than the LDS level-1 sequence: spills into growing pool
+    blocks (values then within tolerance, structure exact)."""
+    A, B = S.crafted_rows([20000, 9000, 70000, 513, 30000], n=60000, dtype=dtype)
+    check(A, B, exact=False)
+
+
+def test_config1_full():
+    A, _ = S.config1()
+    check(A, A)
+
+
+@pytest.mark.parametrize("n,cap", [(3000, 300), (20000, 2000), (50000, 20000)])
+def test_config2_scaled(n, cap):
+    A, _ = S.config2(n=n, cap=cap)
+    check(A, A, exact=False)
+
+
+def test_config3_chain_full():
+    """Both products of the Galerkin chain, checked against the oracle and,
+    through it, against the closed form."""
+    from synthetic import Csr
+    A, P, R = S.config3(64)
+    (rp, ci, v), _ = check(A, P)
+    AP = Csr(A.rows, P.cols, rp, ci, v)
+    check(R, AP)
+
+
+@pytest.mark.parametrize("n", [2000, 20000])
+def test_config5_scaled_f32(n):
+    A, B = S.config5(n=n, ncols=512)
+    check(A, B)
+
+
+def test_config4_sample():
+    probs = S.config4(count=6, nmax=8192)
+    for A, B in probs:
+        check(A, B)
+
+
+def test_degenerate_shapes():
+    from tests.helpers import random_csr
+    rng = np.random.default_rng(5)
+    for m, k, n in [(0, 5, 7), (6, 0, 7), (6, 5, 0), (0, 0, 0), (1, 1, 1)]:
+        A = random_csr(rng, m, k, 0.5)
+        B = random_csr(rng, k, n, 0.5)
+        if A.nnz == 0 and B.nnz == 0 and m * k * n > 0:
+            continue
+        check(A, B)
+    # rows that reference only empty rows of B, and an all-empty product
+    A, B = S.crafted_rows([0, 0, 5, 0], empty_refs=4)
+    check(A, B)
+
+
+def test_zero_products_and_signed_zeros():
+    """Explicit zeros are stored entries; a single product -0.0 must come out
+    as +0.0 (the sum starts from +0.0)."""
+    from tests.helpers import from_rows
+    A = from_rows(3, 3, [(0, 0, -1.0), (0, 1, 0.0), (1, 2, 2.0), (2, 0, 0.0)])
+    B = from_rows(3, 4, [(0, 0, 0.0), (0, 3, 1.0), (1, 0, -3.0), (2, 1, -0.0), (2, 2, 5.0)])
+    (rp, ci, v), _ = check(A, B)
+    assert np.all(np.signbit(v) == np.signbit(oracle.spgemm(A.as_tuple(), B.as_tuple()).val))
+
+
+def test_pool_exhaustion_relaunch():
+    """A pool far too small forces the checkpoint / 2x growth / relaunch path;
+    the result must not change."""
+    A, B = S.crafted_rows([20000, 9000, 3000, 700, 40000, 600], n=60000)
+    (rp0, ci0, v0), i0 = check(A, B, exact=False)
+    (rp1, ci1, v1), i1 = check(A, B, exact=False, pool_entries=300)
+    assert i1.realloc_rounds > 0
+    assert np.array_equal(ci0, ci1) and np.array_equal(v0, v1)
+
+
+def test_options_do_not_change_result():
+    A, _ = S.config2(n=8000, cap=300)
+    (rp0, ci0, v0), _ = check(A, A)
+    (rp1, ci1, v1), _ = check(A, A, bin_edges=(16, 48, 100, 300, 700))
+    (rp2, ci2, v2), _ = check(A, A, bin_edges=(8, 16, 32, 64, 128), l1_cap=7168)
+    for ci, v in ((ci1, v1), (ci2, v2)):
+        assert np.array_equal(ci, ci0) and np.array_equal(v, v0)
+    # a smaller level-1 sequence spills more often: same structure, values
+    # within tolerance (checked inside check())
+    (rp3, ci3, v3), _ = check(A, A, exact=False, long_slot=8, l1_cap=2048)
+    assert np.array_equal(ci3, ci0)
+
+
+def test_row_permutation_equivariance():
+    """Permuting A's rows permutes C's rows; every row is computed the same
+    way, so even spilled rows match bit for bit."""
+    A, _ = S.config2(n=6000, cap=600)
+    (rp, ci, v), _ = check(A, A, exact=False)
+    perm = np.random.default_rng(3).permutation(A.rows)
+    counts = np.diff(A.row_ptr)[perm]
+    rpp = np.zeros(A.rows + 1, np.int32)
+    np.cumsum(counts, out=rpp[1:])
+    idx = np.concatenate([np.arange(A.row_ptr[i], A.row_ptr[i + 1]) for i in perm])
+    from synthetic import Csr
+    Ap = Csr(A.rows, A.cols, rpp, A.col_idx[idx], A.val[idx])
+    (rq, cq, vq), _ = check(Ap, A, exact=False)
+    for newi, oldi in enumerate(perm):
+        a, b = rp[oldi], rp[oldi + 1]
+        c, d = rq[newi], rq[newi + 1]
+        assert np.array_equal(ci[a:b], cq[c:d]) and np.array_equal(v[a:b], vq[c:d])
+
+
+def test_errors():
+    import torch
+    from paper_1504_05022_amd import CsrMatrix, Plan, SpgemmError
+    A, _ = S.config1(n=50, degree=3)
+    dA = CsrMatrix.from_host(A)
+    B = CsrMatrix.from_host(S.uniform_csr(40, 30, 3))
+    with pytest.raises(SpgemmError) as e:
+        Plan(dA, B)
+    assert e.value.name == "EINVAL"
+    d32 = CsrMatrix.from_host(A.astype(np.float32))
+    with pytest.raises(SpgemmError):
+        Plan(dA, d32)
+    # unsorted columns caught by validation
+    bad_ci = A.col_idx.copy()
+    bad_ci[0], bad_ci[1] = bad_ci[1], bad_ci[0]
+    from synthetic import Csr
+    bad = CsrMatrix.from_host(Csr(A.rows, A.cols, A.row_ptr, bad_ci, A.val))
+    with pytest.raises(SpgemmError) as e:
+        Plan(bad, dA, validate=1)
+    assert e.value.name == "EINVAL"
+    # out-of-range column
+    oor = A.col_idx.copy()
+    oor[-1] = A.cols + 5
+    bad2 = CsrMatrix.from_host(Csr(A.rows, A.cols, A.row_ptr, oor, A.val))
+    with pytest.raises(SpgemmError):
+        Plan(bad2, dA, validate=1)
+    # valid input passes validation
+    Plan(dA, dA, validate=1).close()
+    # options out of range
+    with pytest.raises(SpgemmError):
+        Plan(dA, dA, bin_edges=(40, 64, 128, 256, 512))
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_backward_matches_oracle(dtype):
+    import torch
+    from paper_1504_05022_amd import CsrMatrix, Plan
+    A, B = S.config5(n=3000, ncols=256)
+    A, B = A.astype(dtype), B.astype(dtype)
+    dA, dB = CsrMatrix.from_host(A), CsrMatrix.from_host(B)
+    plan = Plan(dA, dB)
+    C = plan.compute()
+    dc = torch.as_tensor(S.config5_dc(C.nnz, dtype=dtype)).cuda()
+    gA, gB = plan.backward(C, dc)
+    torch.cuda.synchronize()
+    ref = oracle.spgemm(A.astype(np.float64).as_tuple(), B.astype(np.float64).as_tuple())
+    ra, rb = oracle.grad(A.as_tuple(), B.as_tuple(), ref.row_ptr, ref.col_idx,
+                         dc.cpu().numpy().astype(np.float64))
+    # componentwise bound: |g - g*| <= tol * sum |terms|
+    absA = np.abs(A.astype(np.float64).val)
+    absB = np.abs(B.astype(np.float64).val)
+    sa, sb = oracle.grad(A.astype(np.float64).as_tuple(),
+                         (B.rows, B.cols, B.row_ptr, B.col_idx, absB),
+                         ref.row_ptr, ref.col_idx, np.abs(dc.cpu().numpy().astype(np.float64)))
+    _, sb = oracle.grad((A.rows, A.cols, A.row_ptr, A.col_idx, absA), B.astype(np.float64).as_tuple(),
+                        ref.row_ptr, ref.col_idx, np.abs(dc.cpu().numpy().astype(np.float64)))
+    tol = TOL[np.dtype(dtype)]
+    assert np.all(np.abs(gA.cpu().numpy().astype(np.float64) - ra) <= tol * sa + 0.0)
+    assert np.all(np.abs(gB.cpu().numpy().astype(np.float64) - rb) <= tol * sb + 0.0)
+    plan.close()
