@@ -30,6 +30,10 @@ struct I32Fn {
   const int32_t *v;
   DEVI int64_t operator()(int64_t e) const { return v[e]; }
 };
+struct PieceFn {
+  const Piece *p;
+  DEVI int64_t operator()(int64_t e) const { return p[e].cnt; }
+};
 
 // Phase 1: sum of every tile.
 template <typename F>
@@ -114,6 +118,10 @@ void scan_i64(const int64_t *v, int64_t n, int64_t *out, int64_t *part, hipStrea
 void scan_i32(const int32_t *v, int64_t n, int64_t *out, int64_t *part, hipStream_t s) {
   scan_with(I32Fn{v}, n, out, part, s);
 }
+void scan_piece_counts(const Piece *pieces, int64_t n, int64_t *out, int64_t *part,
+                       hipStream_t s) {
+  scan_with(PieceFn{pieces}, n, out, part, s);
+}
 
 // ------------------------------------------------------------ validation
 
@@ -169,66 +177,81 @@ template <typename Fn> DEVI void for_each_bin_in_wave(bool valid, int bin, Fn fn
 // Stage 1 result per row and the bin histogram of every wavefront.
 // hist layout: hist[bin * nwaves + wave] so that one exclusive scan yields,
 // for every (bin, wave), the start of that wave's rows in the bin list.
-__global__ __launch_bounds__(256) void k_row_stats(const int32_t *arp, const int64_t *P,
-                                                   int64_t m, int64_t ncols, BinEdges be,
-                                                   int32_t long_slot, int64_t *u, int64_t *h,
-                                                   int32_t *hist, int64_t nwaves,
-                                                   int64_t *rownnz, Summary *sum) {
+// Also per-block sums that size the long-row work (reduced by k_summary).
+__global__ __launch_bounds__(256) void k_row_stats(RowStatsArgs a) {
   __shared__ int32_t cnt[256 / WAVE][NBINS];
+  __shared__ int64_t red[256 / WAVE][kBlockStats];
   const int w = threadIdx.x / WAVE;
   for (int b = lane(); b < NBINS; b += WAVE) cnt[w][b] = 0;
   __syncthreads();
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const bool valid = i < m;
+  const bool valid = i < a.m;
   int64_t ui = 0;
   int bin = 0;
   if (valid) {
-    ui = P[arp[i + 1]] - P[arp[i]];
-    bin = bin_of(ui, be);
-    u[i] = ui;
-    h[i] = bin == LONG_BIN ? static_cast<int64_t>(long_slot) : ui;
-    if (ui == 0) rownnz[i] = 0;
+    ui = a.P[a.arp[i + 1]] - a.P[a.arp[i]];
+    bin = bin_of(ui, a.be);
+    a.u[i] = ui;
+    a.h[i] = bin == LONG_BIN ? static_cast<int64_t>(a.long_slot) : ui;
+    if (ui == 0) a.rownnz[i] = 0;
   }
   for_each_bin_in_wave(valid, bin, [&](int b, uint64_t mask) {
     if (lane() == 0) cnt[w][b] = __popcll(mask);
   });
   __syncthreads();
   const int64_t gw = static_cast<int64_t>(blockIdx.x) * (256 / WAVE) + w;
-  if (gw < nwaves) {
-    for (int b = lane(); b < NBINS; b += WAVE) hist[b * nwaves + gw] = cnt[w][b];
+  if (gw < a.nwaves) {
+    for (int b = lane(); b < NBINS; b += WAVE) a.hist[b * a.nwaves + gw] = cnt[w][b];
   }
-  // largest u: wave max then one atomic per wave
-  unsigned long long mx = static_cast<unsigned long long>(ui);
+  // long-row planning sums
+  int64_t v[kBlockStats];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    unsigned long long y = static_cast<unsigned long long>(
-        __shfl_xor(static_cast<long long>(mx), o, WAVE));
-    mx = mx > y ? mx : y;
+  for (int k = 0; k < kBlockStats; ++k) v[k] = 0;
+  v[0] = ui;
+  if (bin == LONG_BIN) {
+    const int64_t rmax = ui < a.ncols ? ui : a.ncols;
+    int64_t segp;
+    int32_t nseg, shift, npiece;
+    long_row_plan(ui, a.ncols, a.lp, segp, nseg, shift, npiece);
+    v[1] = ui;
+    v[2] = rmax;
+    v[3] = nseg;
+    v[4] = npiece;
+    if (nseg > 1) {
+      v[5] = ui;
+      v[6] = static_cast<int64_t>(nseg) * (npiece + 1);
+      v[8] = rmax;
+    } else if (rmax > a.long_slot) {
+      int64_t cap = a.long_slot;
+      while (cap < rmax) cap *= 2;
+      v[7] = cap;
+    }
+    const int64_t segr = segp < a.ncols ? segp : a.ncols;
+    if (segr > a.l1cap - kLongTile) v[9] = segr * nseg;
   }
-  if (lane() == 0 && mx > 0) atomicMax(&sum->max_u, mx);
-  // products and result bound of the long rows (sizes the long-row pool)
-  long long lu = bin == LONG_BIN ? static_cast<long long>(ui) : 0;
-  long long lr = bin == LONG_BIN ? static_cast<long long>(ui < ncols ? ui : ncols) : 0;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    lu += __shfl_xor(lu, o, WAVE);
-    lr += __shfl_xor(lr, o, WAVE);
+  for (int k = 0; k < kBlockStats; ++k) {
+    int64_t x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int64_t y = __shfl_xor(x, o, WAVE);
+      x = k == 0 ? (x > y ? x : y) : x + y;
+    }
+    if (lane() == 0) red[w][k] = x;
   }
-  if (lane() == 0 && lu > 0) {
-    atomicAdd(reinterpret_cast<unsigned long long *>(&sum->sum_u_long),
-              static_cast<unsigned long long>(lu));
-    atomicAdd(reinterpret_cast<unsigned long long *>(&sum->sum_r_long),
-              static_cast<unsigned long long>(lr));
+  __syncthreads();
+  if (threadIdx.x < kBlockStats) {
+    const int k = threadIdx.x;
+    int64_t x = red[0][k];
+    for (int q = 1; q < 256 / WAVE; ++q) x = k == 0 ? (x > red[q][k] ? x : red[q][k]) : x + red[q][k];
+    a.bpart[static_cast<int64_t>(blockIdx.x) * kBlockStats + k] = x;
   }
 }
 
-void launch_row_stats(const int32_t *arp, const int64_t *P, int64_t m, int64_t ncols,
-                      BinEdges be, int32_t long_slot, int64_t *u, int64_t *h, int32_t *hist,
-                      int64_t nwaves, int64_t *rownnz, Summary *sum, hipStream_t s) {
-  const int64_t nb = (m + 255) / 256;
+void launch_row_stats(const RowStatsArgs &a, hipStream_t s) {
+  const int64_t nb = (a.m + 255) / 256;
   if (nb == 0) return;
-  hipLaunchKernelGGL(k_row_stats, dim3(nb), dim3(256), 0, s, arp, P, m, ncols, be, long_slot, u,
-                     h, hist, nwaves, rownnz, sum);
+  hipLaunchKernelGGL(k_row_stats, dim3(nb), dim3(256), 0, s, a);
 }
 
 // Stable scatter: rows keep ascending order inside each bin.
@@ -257,19 +280,62 @@ void launch_bin_scatter(const int64_t *u, int64_t m, BinEdges be, const int64_t 
                      binlist);
 }
 
-__global__ void k_summary(const int64_t *P, int64_t nnzA, const int64_t *cto, int64_t m,
-                          const int64_t *hist_scan, int64_t nwaves, Summary *sum) {
+__global__ __launch_bounds__(256) void k_summary(const int64_t *P, int64_t nnzA,
+                                                 const int64_t *cto, int64_t m,
+                                                 const int64_t *hist_scan, int64_t nwaves,
+                                                 const int64_t *bpart, int64_t nblocks,
+                                                 Summary *sum) {
+  __shared__ int64_t red[256 / WAVE][kBlockStats];
   const int t = threadIdx.x;
   if (t == 0) {
     sum->sum_u = P[nnzA];
     sum->sum_h = cto[m];
   }
   if (t <= NBINS) sum->bin_off[t] = (t < NBINS) ? hist_scan[t * nwaves] : hist_scan[NBINS * nwaves];
+  int64_t v[kBlockStats];
+#pragma unroll
+  for (int k = 0; k < kBlockStats; ++k) v[k] = 0;
+  for (int64_t b = t; b < nblocks; b += 256) {
+#pragma unroll
+    for (int k = 0; k < kBlockStats; ++k) {
+      const int64_t x = bpart[b * kBlockStats + k];
+      v[k] = k == 0 ? (v[k] > x ? v[k] : x) : v[k] + x;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kBlockStats; ++k) {
+    int64_t x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int64_t y = __shfl_xor(x, o, WAVE);
+      x = k == 0 ? (x > y ? x : y) : x + y;
+    }
+    if (lane() == 0) red[t / WAVE][k] = x;
+  }
+  __syncthreads();
+  if (t < kBlockStats) {
+    int64_t x = red[0][t];
+    for (int q = 1; q < 256 / WAVE; ++q) x = t == 0 ? (x > red[q][t] ? x : red[q][t]) : x + red[q][t];
+    switch (t) {
+      case 0: sum->max_u = static_cast<unsigned long long>(x); break;
+      case 1: sum->sum_u_long = x; break;
+      case 2: sum->sum_r_long = x; break;
+      case 3: sum->n_items = x; break;
+      case 4: sum->n_pieces = x; break;
+      case 5: sum->sum_u_multi = x; break;
+      case 6: sum->n_split = x; break;
+      case 7: sum->pool_single = x; break;
+      case 8: sum->sum_r_multi = x; break;
+      case 9: sum->spill_bound = x; break;
+    }
+  }
 }
 
 void launch_summary(const int64_t *P, int64_t nnzA, const int64_t *cto, int64_t m,
-                    const int64_t *hist_scan, int64_t nwaves, Summary *sum, hipStream_t s) {
-  hipLaunchKernelGGL(k_summary, dim3(1), dim3(64), 0, s, P, nnzA, cto, m, hist_scan, nwaves, sum);
+                    const int64_t *hist_scan, int64_t nwaves, const int64_t *bpart,
+                    int64_t nblocks, Summary *sum, hipStream_t s) {
+  hipLaunchKernelGGL(k_summary, dim3(1), dim3(256), 0, s, P, nnzA, cto, m, hist_scan, nwaves,
+                     bpart, nblocks, sum);
 }
 
 __global__ void k_fill_i64(int64_t *p, int64_t n, int64_t v) {
@@ -299,9 +365,16 @@ void launch_zero(void *p, size_t bytes, hipStream_t s) {
   hipLaunchKernelGGL(k_zero, dim3(nb), dim3(256), 0, s, static_cast<uint32_t *>(p), n);
 }
 
+__global__ void k_set_pool(Pool *dst, Pool value) { *dst = value; }
+
+void launch_set_pool(Pool *dst, Pool value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_pool, dim3(1), dim3(1), 0, s, dst, value);
+}
+
 __global__ void k_status(const int64_t *rowoff, int64_t m, const Pool *pool, ComputeStatus *st) {
   st->nnz_c = rowoff[m];
   st->fail_count = pool->fail_count;
+  st->fail2 = pool->fail2;
   st->pool_used = pool->used;
 }
 

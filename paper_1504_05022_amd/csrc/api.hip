@@ -121,6 +121,34 @@ int check_csr(const spgemm_csr *M, const char *name) {
   return SPGEMM_OK;
 }
 
+// Pinned staging for the small device<->host records, one per thread,
+// allocated once (hipHostMalloc is far too slow to call per plan).
+void *pinned_staging() {
+  thread_local void *buf = nullptr;
+  if (!buf) {
+    if (hipHostMalloc(&buf, 4096, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      buf = nullptr;
+    }
+  }
+  return buf;
+}
+
+// Device -> host copy of a small record through the pinned staging area;
+// synchronizes the stream.
+hipError_t read_small(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  void *stage = pinned_staging();
+  if (!stage || bytes > 4096) {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+  }
+  hipError_t e = hipMemcpyAsync(stage, src, bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) std::memcpy(dst, stage, bytes);
+  return e;
+}
+
 }  // namespace
 
 struct spgemm_plan_s {
@@ -139,15 +167,22 @@ struct spgemm_plan_s {
   int64_t *P = nullptr, *u = nullptr, *h = nullptr, *cto = nullptr, *rownnz = nullptr,
           *rowoff = nullptr, *hist_scan = nullptr, *part = nullptr;
   int32_t *hist = nullptr, *binlist = nullptr;
+  int64_t *bpart = nullptr;
+  int64_t nblocks = 0;
+  LongParams lp{};
+  int l1cap = 0;
   Summary *dsum = nullptr;
   ComputeStatus *dstat = nullptr;
   Pool *dpool = nullptr;
   int64_t nwaves = 0;
 
-  // pinned host mirrors
+  // host mirrors
   Summary *hsum = nullptr;
   ComputeStatus *hstat = nullptr;
   Pool *hpool = nullptr;
+  Summary hsum_store{};
+  ComputeStatus hstat_store{};
+  Pool hpool_store{};
 
   // compute scratch
   void *cws = nullptr;
@@ -177,7 +212,7 @@ void spgemm_default_options(spgemm_options *o) {
   o->bin_edges[4] = 512;
   o->long_slot = 256;
   o->l1_cap = 0;
-  o->seg = -1;
+  o->seg = 0;
   o->pool_entries = 0;
   o->validate = 0;
   o->timing = 0;
@@ -214,7 +249,6 @@ void destroy_plan(spgemm_plan p) {
   release_compute(p, p->stream);
   p->al.put(p->ws, p->stream);
   p->al.put(p->bws, p->stream);
-  if (p->hsum) (void)hipHostFree(p->hsum);
   if (p->events)
     for (auto &e : p->ev) (void)hipEventDestroy(e);
   for (auto &e : p->long_ev) (void)hipEventDestroy(e);
@@ -286,6 +320,13 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
 
   const int64_t m = p->m;
   p->nwaves = (m + 63) / 64;  // one histogram column per 64-row wavefront
+  p->nblocks = (m + 255) / 256;
+  p->l1cap = o.l1_cap ? o.l1_cap : long_l1cap_default(dtype_bytes(p->dtype));
+  p->lp.segp = o.seg < 0 ? -1 : (o.seg > 0 ? o.seg : p->l1cap - kLongTile);
+  p->lp.maxs = combine_maxs();
+  p->lp.cb = 2048;
+  p->lp.minw_shift = 4;
+  p->lp.maxw_shift = 30;
   const int64_t nh = static_cast<int64_t>(NBINS) * p->nwaves;
   int64_t partn = scan_part_len(std::max<int64_t>({p->nnzA, m, nh, 1}));
   Layout L;
@@ -299,6 +340,7 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   const size_t opart = L.add<int64_t>(partn);
   const size_t ohist = L.add<int32_t>(nh);
   const size_t obl = L.add<int32_t>(m);
+  const size_t obp = L.add<int64_t>(p->nblocks * kBlockStats);
   const size_t osum = L.add<Summary>(1);
   const size_t ostat = L.add<ComputeStatus>(1);
   const size_t opool = L.add<Pool>(1);
@@ -318,24 +360,15 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   p->part = at<int64_t>(p->ws, opart);
   p->hist = at<int32_t>(p->ws, ohist);
   p->binlist = at<int32_t>(p->ws, obl);
+  p->bpart = at<int64_t>(p->ws, obp);
   p->dsum = at<Summary>(p->ws, osum);
   p->dstat = at<ComputeStatus>(p->ws, ostat);
   p->dpool = at<Pool>(p->ws, opool);
 
-  // pinned host mirrors of the small records
-  {
-    void *hp = nullptr;
-    hipError_t e = hipHostMalloc(&hp, sizeof(Summary) + sizeof(ComputeStatus) + sizeof(Pool) + 64,
-                                 hipHostMallocDefault);
-    if (e != hipSuccess) {
-      destroy_plan(p);
-      return hip_fail(e, "hipHostMalloc");
-    }
-    p->hsum = static_cast<Summary *>(hp);
-    p->hstat = reinterpret_cast<ComputeStatus *>(static_cast<char *>(hp) + sizeof(Summary));
-    p->hpool = reinterpret_cast<Pool *>(static_cast<char *>(hp) + sizeof(Summary) +
-                                        sizeof(ComputeStatus));
-  }
+  // host mirrors of the small records (read-backs go through pinned staging)
+  p->hsum = &p->hsum_store;
+  p->hstat = &p->hstat_store;
+  p->hpool = &p->hpool_store;
   if (o.timing) {
     for (auto &e : p->ev) {
       if (hipEventCreate(&e) != hipSuccess) {
@@ -351,8 +384,7 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
     // checked before any kernel indexes with the inputs
     launch_validate(A->row_ptr, A->col_idx, A->rows, A->cols, A->nnz, p->dsum, s);
     launch_validate(B->row_ptr, B->col_idx, B->rows, B->cols, B->nnz, p->dsum, s);
-    hipError_t ve = hipMemcpyAsync(p->hsum, p->dsum, sizeof(Summary), hipMemcpyDeviceToHost, s);
-    if (ve == hipSuccess) ve = hipStreamSynchronize(s);
+    hipError_t ve = read_small(p->hsum, p->dsum, sizeof(Summary), s);
     if (ve != hipSuccess) {
       destroy_plan(p);
       return hip_fail(ve, "validate");
@@ -366,18 +398,34 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   // stage 1 (Algorithm 2): P = exclusive scan of nnz(b_j*) over A's entries,
   // so u_i = P[arp[i+1]] - P[arp[i]].
   scan_row_lengths(A->col_idx, B->row_ptr, p->nnzA, p->P, p->part, s);
-  launch_row_stats(A->row_ptr, p->P, m, p->n, p->be, o.long_slot, p->u, p->h, p->hist, p->nwaves,
-                   p->rownnz, p->dsum, s);
+  {
+    RowStatsArgs ra;
+    ra.arp = A->row_ptr;
+    ra.P = p->P;
+    ra.m = m;
+    ra.ncols = p->n;
+    ra.be = p->be;
+    ra.long_slot = o.long_slot;
+    ra.l1cap = p->l1cap;
+    ra.lp = p->lp;
+    ra.u = p->u;
+    ra.h = p->h;
+    ra.hist = p->hist;
+    ra.nwaves = p->nwaves;
+    ra.rownnz = p->rownnz;
+    ra.bpart = p->bpart;
+    launch_row_stats(ra, s);
+  }
   stage_end(p, SPGEMM_T_UPPER, s);
   // stage 2 (Algorithm 3): C~ offsets and the stable bin lists
   stage_begin(p, SPGEMM_T_BIN, s);
   scan_i64(p->h, m, p->cto, p->part, s);
   scan_i32(p->hist, nh, p->hist_scan, p->part, s);
   launch_bin_scatter(p->u, m, p->be, p->hist_scan, p->nwaves, p->binlist, s);
-  launch_summary(p->P, p->nnzA, p->cto, m, p->hist_scan, p->nwaves, p->dsum, s);
+  launch_summary(p->P, p->nnzA, p->cto, m, p->hist_scan, p->nwaves, p->bpart, p->nblocks,
+                 p->dsum, s);
   stage_end(p, SPGEMM_T_BIN, s);
-  hipError_t e = hipMemcpyAsync(p->hsum, p->dsum, sizeof(Summary), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipError_t e = read_small(p->hsum, p->dsum, sizeof(Summary), s);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) {
     destroy_plan(p);
@@ -387,6 +435,10 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   if (S.err) {
     destroy_plan(p);
     return fail(SPGEMM_EINVAL, "input CSR failed validation (row_ptr or column order/range)");
+  }
+  if (S.max_u >= (1ull << 31)) {
+    destroy_plan(p);
+    return fail(SPGEMM_EOVERFLOW, "a row of C has 2^31 or more products");
   }
   spgemm_info &I = p->info;
   std::memset(&I, 0, sizeof(I));
@@ -399,7 +451,7 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   I.nnz_c = -1;
   I.max_u = static_cast<int64_t>(S.max_u);
   for (int b = 0; b < NBINS; ++b) I.bin_count[b] = S.bin_off[b + 1] - S.bin_off[b];
-  I.long_items = I.bin_count[LONG_BIN];
+  I.long_items = S.n_items;
   I.bytes_scratch = static_cast<int64_t>(p->ws_bytes);
   if (p->events) {
     (void)hipEventElapsedTime(&I.stage_ms[SPGEMM_T_UPPER], p->ev[0], p->ev[1]);
@@ -421,27 +473,57 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   const int64_t nlong = I.bin_count[LONG_BIN];
   release_compute(p, s);
 
-  // C~ (hybrid sizes) plus the long-row records in one allocation
+  // C~ (hybrid sizes) plus the long-row tables in one allocation
+  const int64_t nitems = nlong > 0 ? S.n_items : 0;
+  const int64_t npieces = nlong > 0 ? S.n_pieces : 0;
   Layout L;
   const size_t octc = L.add<int32_t>(S.sum_h);
   const size_t octv = L.add<T>(S.sum_h);
-  const size_t oit = L.add<LongItem>(nlong);
-  const size_t ost = L.add<LongState>(nlong);
-  const size_t ofa = L.add<unsigned int>(nlong);
-  const size_t ofb = L.add<unsigned int>(nlong);
-  const size_t orc = L.add<int32_t *>(nlong > 0 ? m : 0);
-  const size_t orv = L.add<T *>(nlong > 0 ? m : 0);
+  const size_t olr = L.add<LongRow>(nlong);
+  const size_t oit = L.add<LongItem>(nitems);
+  const size_t ost = L.add<LongState>(nitems);
+  const size_t opa = L.add<Seq>(nitems);
+  const size_t ofa = L.add<unsigned int>(nitems);
+  const size_t ofb = L.add<unsigned int>(nitems);
+  const size_t ocs = L.add<LongState>(npieces);
+  const size_t of2a = L.add<unsigned int>(npieces);
+  const size_t of2b = L.add<unsigned int>(npieces);
+  const size_t opc = L.add<Piece>(npieces);
+  const size_t opl = L.add<int32_t>(npieces);
+  const size_t ops = L.add<int64_t>(npieces + 1);
+  const size_t opp = L.add<int64_t>(scan_part_len(std::max<int64_t>(npieces, 1)));
+  const size_t osp = L.add<int32_t>(nlong > 0 ? S.n_split : 0);
+  const size_t opbc = L.add<int32_t>(nlong > 0 ? S.sum_u_multi : 0);
+  const size_t opbv = L.add<T>(nlong > 0 ? S.sum_u_multi : 0);
+  const size_t otmp = L.add<int64_t>(long_table_tmp_len(nlong));
+  const size_t ocnt = L.add<LongCounters>(1);
+  const size_t ogl = L.add<unsigned int>(nitems);
+  const size_t ogl2 = L.add<unsigned int>(npieces);
   p->cws_bytes = L.bytes();
   p->cws = p->al.get(p->cws_bytes, s);
   if (!p->cws) return fail(SPGEMM_ENOMEM, "C~ allocation failed");
   int32_t *ct_col = at<int32_t>(p->cws, octc);
   T *ct_val = at<T>(p->cws, octv);
+  LongRow *lrows = at<LongRow>(p->cws, olr);
   LongItem *items = at<LongItem>(p->cws, oit);
   LongState *states = at<LongState>(p->cws, ost);
+  Seq *partials = at<Seq>(p->cws, opa);
   unsigned int *fail_a = at<unsigned int>(p->cws, ofa);
   unsigned int *fail_b = at<unsigned int>(p->cws, ofb);
-  int32_t **rsrc_col = at<int32_t *>(p->cws, orc);
-  T **rsrc_val = at<T *>(p->cws, orv);
+  LongState *cstates = at<LongState>(p->cws, ocs);
+  unsigned int *fail2_a = at<unsigned int>(p->cws, of2a);
+  unsigned int *fail2_b = at<unsigned int>(p->cws, of2b);
+  Piece *pieces = at<Piece>(p->cws, opc);
+  int32_t *piece_lrow = at<int32_t>(p->cws, opl);
+  int64_t *pscan = at<int64_t>(p->cws, ops);
+  int64_t *ppart = at<int64_t>(p->cws, opp);
+  int32_t *split = at<int32_t>(p->cws, osp);
+  int32_t *pcol = at<int32_t>(p->cws, opbc);
+  T *pval = at<T>(p->cws, opbv);
+  int64_t *lt_tmp = at<int64_t>(p->cws, otmp);
+  LongCounters *lcnt = at<LongCounters>(p->cws, ocnt);
+  unsigned int *glist = at<unsigned int>(p->cws, ogl);
+  unsigned int *glist2 = at<unsigned int>(p->cws, ogl2);
 
   EscArgs<T> ea;
   ea.arp = A->row_ptr;
@@ -481,71 +563,141 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   }
   stage_end(p, SPGEMM_T_MEDIUM, s);
 
-  // ---- bin group 5: long rows with the merge method and a growing pool
+  // ---- bin group 5: long rows (merge method, split over work-groups)
   int64_t pool_entries = 0;
   I.realloc_rounds = 0;
   I.long_launches = 0;
   I.long_kernel_ms = 0.f;
-  const int l1cap = p->opt.l1_cap ? p->opt.l1_cap : long_l1cap_default(sizeof(T));
   LongArgs<T> la;
   la.e = ea;
+  la.lrows = lrows;
   la.items = items;
+  la.work = nullptr;
   la.state = states;
   la.pool = p->dpool;
+  la.fail_list = fail_a;
   la.long_slot = p->opt.long_slot;
-  la.rsrc_col = rsrc_col;
-  la.rsrc_val = rsrc_val;
+  la.partials = partials;
+  la.pcol = pcol;
+  la.pval = pval;
+  la.split = split;
+  la.pieces = pieces;
+  la.piece_lrow = piece_lrow;
+  la.cstate = cstates;
+  la.fail_list2 = fail2_a;
+  la.cnt = lcnt;
+  la.glist = glist;
+  la.glist2 = glist2;
+  la.ncols = p->n;
+  const bool spill_expected = S.spill_bound > 0 || p->opt.pool_entries > 0;
+  auto new_pool = [&](int64_t entries, unsigned long long used) -> int {
+    void *chunk = p->al.get(pool_chunk_bytes(entries, sizeof(T)), s);
+    if (!chunk) return fail(SPGEMM_ENOMEM, "long-row pool allocation failed");
+    p->pool_chunks.push_back(chunk);
+    *p->hpool = pool_view(chunk, entries);
+    p->hpool->used = used;
+    launch_set_pool(p->dpool, *p->hpool, s);
+    return SPGEMM_OK;
+  };
+  auto read_status = [&]() -> int {
+    launch_status(p->rowoff, m, p->dpool, p->dstat, s);
+    HIP_TRY(read_small(p->hstat, p->dstat, sizeof(ComputeStatus), s));
+    HIP_TRY(hipGetLastError());
+    return SPGEMM_OK;
+  };
+  auto finish_long = [&]() {
+    // long-row sizes from their pieces
+    scan_piece_counts(pieces, npieces, pscan, ppart, s);
+    launch_long_rownnz(lrows, nlong, pscan, p->rownnz, s);
+  };
+  int rc;
   if (nlong > 0) {
     pool_entries = p->opt.pool_entries
                        ? p->opt.pool_entries
-                       : std::max<int64_t>(3 * S.sum_r_long + nlong * p->opt.long_slot, 1 << 16);
-    void *chunk = p->al.get(pool_chunk_bytes(pool_entries, sizeof(T)), s);
-    if (!chunk) return fail(SPGEMM_ENOMEM, "long-row pool allocation failed");
-    p->pool_chunks.push_back(chunk);
-    *p->hpool = pool_view(chunk, pool_entries);
-    HIP_TRY(hipMemcpyAsync(p->dpool, p->hpool, sizeof(Pool), hipMemcpyHostToDevice, s));
-    launch_long_items(p->binlist, S.bin_off[LONG_BIN], nlong, p->u, items, s);
-    launch_long_init(items, states, nlong, s);
+                       : S.pool_single + S.sum_r_multi + 3 * S.spill_bound + 65536;
+    if ((rc = new_pool(pool_entries, 0)) != SPGEMM_OK) return rc;
+    launch_long_table(p->binlist, S.bin_off[LONG_BIN], nlong, p->u, p->n, p->lp, lrows, items,
+                      states, partials, piece_lrow, lt_tmp, s);
+    launch_item_entry(A->row_ptr, p->P, items, nitems, s);
+    launch_cstate_init(cstates, npieces, s);
+    launch_zero(lcnt, sizeof(LongCounters), s);
+    // phase 1: every segment; one tile when small enough, else the level-1
+    // merge method
+    stage_begin(p, SPGEMM_T_LONG, s);
+    launch_long_oneshot<T>(la, nitems, s);
+    if (launch_long<T>(la, nitems, p->l1cap, s))
+      return fail(SPGEMM_EINVAL, "no long-row kernel for this l1_cap");
+    I.long_launches++;
+    stage_end(p, SPGEMM_T_LONG, s);
+    // pool exhaustion in phase 1 only when L1 can spill: relaunch from checkpoints
+    if (spill_expected) {
+      unsigned int *fl = fail_a, *fl_other = fail_b;
+      for (;;) {
+        if ((rc = read_status()) != SPGEMM_OK) return rc;
+        const unsigned int nfail = p->hstat->fail_count;
+        if (nfail == 0) break;
+        if (++I.realloc_rounds > 64) return fail(SPGEMM_ENOMEM, "long-row pool keeps overflowing");
+        pool_entries *= 2;
+        if ((rc = new_pool(pool_entries, p->hstat->pool_used)) != SPGEMM_OK) return rc;
+        la.work = reinterpret_cast<const int32_t *>(fl);
+        la.fail_list = fl_other;
+        if (launch_long<T>(la, nfail, p->l1cap, s))
+          return fail(SPGEMM_EINVAL, "no long-row kernel for this l1_cap");
+        I.long_launches++;
+        std::swap(fl, fl_other);
+      }
+      la.work = nullptr;
+      la.fail_list = fail_a;
+    }
+    // phase 2: every output piece of the multi-segment rows
+    if (S.sum_u_multi > 0) {
+      launch_combine_oneshot<T>(la, npieces, s);
+      launch_combine<T>(la, npieces, s);
+    }
+    finish_long();
   }
-  int64_t nwork = nlong;
-  const unsigned int *work = nullptr;
-  unsigned int *fl = fail_a, *fl_other = fail_b;
-  for (int round = 0;; ++round) {
-    if (round == 0) stage_begin(p, SPGEMM_T_LONG, s);
-    if (nwork > 0) {
-      la.work = reinterpret_cast<const int32_t *>(work);
-      la.fail_list = fl;
-      if (launch_long<T>(la, nwork, p->n, l1cap, s))
-        return fail(SPGEMM_EINVAL, "no long-row kernel for this l1_cap");
-      I.long_launches++;
+
+  // ---- stage 4a: row pointers of C (exclusive scan of the row sizes)
+  stage_begin(p, SPGEMM_T_SCAN, s);
+  scan_i64(p->rownnz, m, p->rowoff, p->part, s);
+  stage_end(p, SPGEMM_T_SCAN, s);
+  {
+    unsigned int *f2 = fail2_a, *f2_other = fail2_b;
+    unsigned int *fl = fail_a, *fl_other = fail_b;
+    for (;;) {
+      if ((rc = read_status()) != SPGEMM_OK) return rc;
+      const unsigned int nf1 = nlong > 0 ? p->hstat->fail_count : 0u;
+      const unsigned int nf2 = nlong > 0 ? p->hstat->fail2 : 0u;
+      if (nf1 == 0 && nf2 == 0) break;
+      if (++I.realloc_rounds > 64) return fail(SPGEMM_ENOMEM, "long-row pool keeps overflowing");
+      pool_entries *= 2;
+      if ((rc = new_pool(pool_entries, p->hstat->pool_used)) != SPGEMM_OK) return rc;
+      if (nf1 > 0) {
+        // phase-1 items resume from their checkpoints; phase 2 then reruns
+        la.work = reinterpret_cast<const int32_t *>(fl);
+        la.fail_list = fl_other;
+        launch_long<T>(la, nf1, p->l1cap, s);
+        I.long_launches++;
+        std::swap(fl, fl_other);
+        la.work = nullptr;
+        la.fail_list = fl;
+        launch_cstate_init(cstates, npieces, s);
+        launch_zero(lcnt, sizeof(LongCounters), s);
+        la.fail_list2 = f2;
+        if (S.sum_u_multi > 0) {
+          launch_combine_oneshot<T>(la, npieces, s);
+          launch_combine<T>(la, npieces, s);
+        }
+      } else {
+        la.work = reinterpret_cast<const int32_t *>(f2);
+        la.fail_list2 = f2_other;
+        launch_combine<T>(la, nf2, s);
+        std::swap(f2, f2_other);
+        la.work = nullptr;
+      }
+      finish_long();
+      scan_i64(p->rownnz, m, p->rowoff, p->part, s);
     }
-    if (round == 0) {
-      stage_end(p, SPGEMM_T_LONG, s);
-      stage_begin(p, SPGEMM_T_SCAN, s);
-    }
-    // ---- stage 4a: row pointers of C (exclusive scan of the row sizes)
-    scan_i64(p->rownnz, m, p->rowoff, p->part, s);
-    launch_status(p->rowoff, m, p->dpool, p->dstat, s);
-    if (round == 0) stage_end(p, SPGEMM_T_SCAN, s);
-    HIP_TRY(hipMemcpyAsync(p->hstat, p->dstat, sizeof(ComputeStatus), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(hipGetLastError());
-    const unsigned int nfail = nlong > 0 ? p->hstat->fail_count : 0u;
-    if (nfail == 0) break;
-    // pool exhausted: grow 2x, relaunch the failed items from their checkpoints
-    I.realloc_rounds++;
-    if (I.realloc_rounds > 64) return fail(SPGEMM_ENOMEM, "long-row pool keeps overflowing");
-    const unsigned long long used = p->hstat->pool_used;
-    pool_entries *= 2;
-    void *chunk = p->al.get(pool_chunk_bytes(pool_entries, sizeof(T)), s);
-    if (!chunk) return fail(SPGEMM_ENOMEM, "long-row pool growth failed");
-    p->pool_chunks.push_back(chunk);
-    *p->hpool = pool_view(chunk, pool_entries);
-    p->hpool->used = used;
-    HIP_TRY(hipMemcpyAsync(p->dpool, p->hpool, sizeof(Pool), hipMemcpyHostToDevice, s));
-    work = fl;
-    nwork = nfail;
-    std::swap(fl, fl_other);
   }
   const int64_t nnz = p->hstat->nnz_c;
   if (nnz >= (int64_t(1) << 31)) return fail(SPGEMM_EOVERFLOW, "nnz(C) exceeds 2^31 - 1");
@@ -567,15 +719,16 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   ca.cto = p->cto;
   ca.ct_col = ct_col;
   ca.ct_val = ct_val;
-  ca.rsrc_col = rsrc_col;
-  ca.rsrc_val = rsrc_val;
   ca.rowoff = p->rowoff;
   ca.long_min = p->be.e[4];
+  ca.lrows = lrows;
+  ca.pieces = pieces;
+  ca.pscan = pscan;
   ca.c_rp = static_cast<int32_t *>(crp);
   ca.c_col = static_cast<int32_t *>(ccol);
   ca.c_val = static_cast<T *>(cval);
   if (m > 0)
-    launch_compact<T>(ca, m, s);
+    launch_compact<T>(ca, m, npieces, s);
   else
     launch_zero(crp, 4, s);
   stage_end(p, SPGEMM_T_COPY, s);

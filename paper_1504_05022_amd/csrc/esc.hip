@@ -109,38 +109,20 @@ __global__ __launch_bounds__(ESC_NT) void k_esc(EscArgs<T> a, const int32_t *row
 
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) sk[pos * K + kk] = key[kk];
-    Key pk = shfl_up_key<Key>(key[K - 1], 1);
+    const Key pk = shfl_up_key<Key>(key[K - 1], 1);
     __syncthreads();
 
-    // compress: fold every column's products in expansion order
+    // compress: count the distinct columns, place them with a group scan,
+    // then fold every column's products in expansion order
+    uint32_t hmask = 0;
     int nh = 0;
-    bool hd[K];
-    int32_t hc[K];
-    T hv[K];
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) {
       const int l = pos * K + kk;
-      hd[kk] = false;
-      hc[kk] = 0;
-      hv[kk] = T(0);
-      if (l < u) {
-        const Key c = key[kk] >> LOGU;
-        const Key before = kk > 0 ? key[kk - 1] : pk;
-        const bool head = (l == 0) || ((before >> LOGU) != c);
-        if (head) {
-          T v = T(0);
-          v = v + pv[static_cast<int>(key[kk] & (U - 1))];
-          for (int l2 = l + 1; l2 < u; ++l2) {
-            const Key k2 = sk[l2];
-            if ((k2 >> LOGU) != c) break;
-            v = v + pv[static_cast<int>(k2 & (U - 1))];
-          }
-          hd[kk] = true;
-          hc[kk] = static_cast<int32_t>(c);
-          hv[kk] = v;
-          ++nh;
-        }
-      }
+      const Key before = kk > 0 ? key[kk - 1] : pk;
+      const bool head = l < u && (l == 0 || (before >> LOGU) != (key[kk] >> LOGU));
+      hmask |= head ? (1u << kk) : 0u;
+      nh += head ? 1 : 0;
     }
     const int incl_h = group_incl_sum<G>(nh);
     const int total = group_last<G>(incl_h);
@@ -148,9 +130,18 @@ __global__ __launch_bounds__(ESC_NT) void k_esc(EscArgs<T> a, const int32_t *row
       int64_t o = a.cto[i] + (incl_h - nh);
 #pragma unroll
       for (int kk = 0; kk < K; ++kk) {
-        if (hd[kk]) {
-          a.ct_col[o] = hc[kk];
-          a.ct_val[o] = hv[kk];
+        if (hmask & (1u << kk)) {
+          const int l = pos * K + kk;
+          const Key c = key[kk] >> LOGU;
+          T v = T(0);
+          v = v + pv[static_cast<int>(key[kk] & (U - 1))];
+          for (int l2 = l + 1; l2 < u; ++l2) {
+            const Key k2 = sk[l2];
+            if ((k2 >> LOGU) != c) break;
+            v = v + pv[static_cast<int>(k2 & (U - 1))];
+          }
+          a.ct_col[o] = static_cast<int32_t>(c);
+          a.ct_val[o] = v;
           ++o;
         }
       }
@@ -177,16 +168,18 @@ template <typename T>
 int launch_esc(const EscArgs<T> &a, const int32_t *rows, int64_t nrows, int cap, int64_t ncols,
                hipStream_t s) {
   if (nrows <= 0) return 0;
+  // lanes per row G and products per lane K for each capacity: several
+  // rows per wavefront so that their memory latencies overlap
   switch (cap) {
     case 1: launch_gk<T, 1, 1>(a, rows, nrows, ncols, s); break;
     case 2: launch_gk<T, 2, 1>(a, rows, nrows, ncols, s); break;
     case 4: launch_gk<T, 4, 1>(a, rows, nrows, ncols, s); break;
-    case 8: launch_gk<T, 8, 1>(a, rows, nrows, ncols, s); break;
-    case 16: launch_gk<T, 16, 1>(a, rows, nrows, ncols, s); break;
-    case 32: launch_gk<T, 32, 1>(a, rows, nrows, ncols, s); break;
-    case 64: launch_gk<T, 64, 1>(a, rows, nrows, ncols, s); break;
-    case 128: launch_gk<T, 64, 2>(a, rows, nrows, ncols, s); break;
-    case 256: launch_gk<T, 64, 4>(a, rows, nrows, ncols, s); break;
+    case 8: launch_gk<T, 4, 2>(a, rows, nrows, ncols, s); break;
+    case 16: launch_gk<T, 4, 4>(a, rows, nrows, ncols, s); break;
+    case 32: launch_gk<T, 8, 4>(a, rows, nrows, ncols, s); break;
+    case 64: launch_gk<T, 16, 4>(a, rows, nrows, ncols, s); break;
+    case 128: launch_gk<T, 16, 8>(a, rows, nrows, ncols, s); break;
+    case 256: launch_gk<T, 32, 8>(a, rows, nrows, ncols, s); break;
     case 512: launch_gk<T, 64, 8>(a, rows, nrows, ncols, s); break;
     case 1024: launch_gk<T, 64, 16>(a, rows, nrows, ncols, s); break;
     default: return -1;

@@ -38,16 +38,112 @@ struct Summary {
   int64_t bin_off[NBINS + 1]; // start of every bin's segment in the row list
   int64_t sum_u_long;         // sum of u_i over long rows (bin 37)
   int64_t sum_r_long;         // sum of min(u_i, n) over long rows
+  int64_t n_items;            // long-row work items
+  int64_t n_pieces;           // long-row output pieces
+  int64_t sum_u_multi;        // sum of u_i over rows split into several items
+  int64_t n_split;            // range-start table entries (multi-item rows)
+  int64_t pool_single;        // pool entries for one-item rows' final blocks
+  int64_t sum_r_multi;        // sum of min(u_i, n) over multi-item rows
+  int64_t spill_bound;        // sum of min(segment, n) over items that may spill L1
   int32_t err;                // nonzero: input validation failed
   int32_t pad;
+};
+
+// Splitting of long rows (bin 37) into work items and output pieces.
+//  * a row with u products is cut into nseg product segments of at most segp
+//    consecutive products (expansion order); each segment is one work item
+//    of the merge-method kernel and yields a sorted, duplicate-free partial;
+//  * a row with one segment is finished by that item (one output piece);
+//  * a row with several segments is finished by combine work-groups, one
+//    per column range of width 2^shift (npiece ranges), each folding the
+//    ranges of all partials in segment order into one output piece.
+struct LongParams {
+  int64_t segp;      // products per segment; < 0: never split
+  int32_t maxs;      // at most this many segments per row (segp grows)
+  int32_t cb;        // target entries per combine range
+  int32_t minw_shift;
+  int32_t maxw_shift;  // combine ranges are at most the level-1 capacity
+};
+
+__host__ __device__ inline int32_t ceil_log2_i64(int64_t x) {
+  int32_t s = 0;
+  while ((int64_t(1) << s) < x) ++s;
+  return s;
+}
+
+__host__ __device__ inline void long_row_plan(int64_t u, int64_t n, const LongParams &lp,
+                                              int64_t &segp, int32_t &nseg, int32_t &shift,
+                                              int32_t &npiece) {
+  if (lp.segp < 0 || u <= lp.segp) {
+    segp = u > 0 ? u : 1;
+    nseg = 1;
+    shift = 0;
+    npiece = 1;
+    return;
+  }
+  segp = lp.segp;
+  const int64_t need = (u + lp.maxs - 1) / lp.maxs;
+  if (need > segp) segp = need;
+  nseg = static_cast<int32_t>((u + segp - 1) / segp);
+  if (nseg <= 1) {
+    segp = u;
+    nseg = 1;
+    shift = 0;
+    npiece = 1;
+    return;
+  }
+  const int64_t w = (n * lp.cb + u - 1) / u;
+  shift = ceil_log2_i64(w > 1 ? w : 1);
+  if (shift < lp.minw_shift) shift = lp.minw_shift;
+  if (shift > lp.maxw_shift) shift = lp.maxw_shift;
+  npiece = static_cast<int32_t>((n + (int64_t(1) << shift) - 1) >> shift);
+  if (npiece < 1) npiece = 1;
+}
+
+struct LongRow {
+  int32_t row;
+  int32_t nseg;
+  int32_t npiece;
+  int32_t shift;
+  int64_t u;
+  int64_t segp;
+  int64_t item0;   // first work item
+  int64_t piece0;  // first output piece
+  int64_t pbase;   // offset of the row's partials (multi-segment rows)
+  int64_t sbase;   // offset of the row's range-start table (multi-segment rows)
 };
 
 // A long-row work item: products [p0, p1) of row `row` (positions in the
 // row's expansion order: ascending j, then ascending k inside b_j*).
 struct LongItem {
   int32_t row;
-  int32_t part;  // index of this piece within its row (0 if unsplit)
+  int32_t lrow;     // index in the long-row table
   int64_t p0, p1;
+  int32_t e_first;  // entry of A's row containing product p0
+  int32_t pad;
+};
+
+// Work the one-tile kernels leave to the general kernels.
+struct LongCounters {
+  unsigned int glong;
+  unsigned int gcomb;
+};
+
+// Sorted, duplicate-free sequence in device memory.
+struct Seq {
+  int32_t *col;
+  void *val;
+  int64_t cnt;
+};
+
+// One output piece of a long row: `cnt` entries to be copied to C at
+// row offset + (pieces of the same row before it).
+struct Piece {
+  int32_t *col;
+  void *val;
+  int64_t cnt;
+  int32_t lrow;
+  int32_t pad;
 };
 
 // Checkpoint of a long-row work item (resumable after pool exhaustion).
@@ -70,8 +166,8 @@ struct Pool {
   void *val;
   unsigned long long cap;     // entries
   unsigned long long top;     // next free entry (atomic)
-  unsigned int fail_count;    // work items that failed to obtain a block
-  unsigned int pad;
+  unsigned int fail_count;    // phase-1 work items that failed to obtain a block
+  unsigned int fail2;         // combine pieces that failed to obtain a block
   unsigned long long used;    // entries handed out successfully
 };
 
@@ -79,7 +175,7 @@ struct Pool {
 struct ComputeStatus {
   int64_t nnz_c;
   unsigned int fail_count;
-  unsigned int pad;
+  unsigned int fail2;
   unsigned long long pool_used;
 };
 
@@ -104,14 +200,30 @@ void launch_validate(const int32_t *rp, const int32_t *ci, int64_t rows, int64_t
 
 // Stage 1 per row: u_i from the scanned row lengths, C~ row sizes, bin
 // histograms per wavefront; zeroes nnz of empty rows.
-void launch_row_stats(const int32_t *arp, const int64_t *P, int64_t m, int64_t ncols,
-                      BinEdges be, int32_t long_slot, int64_t *u, int64_t *h, int32_t *hist,
-                      int64_t nwaves, int64_t *rownnz, Summary *sum, hipStream_t s);
+struct RowStatsArgs {
+  const int32_t *arp;
+  const int64_t *P;
+  int64_t m, ncols;
+  BinEdges be;
+  int32_t long_slot;
+  int32_t l1cap;
+  LongParams lp;
+  int64_t *u, *h;
+  int32_t *hist;
+  int64_t nwaves;
+  int64_t *rownnz;
+  int64_t *bpart;  // per-block partial sums, kBlockStats per block
+};
+// per block: max u, sum u (long), sum min(u,n) (long), items, pieces,
+// sum u (multi), split entries, pool (single), sum min(u,n) (multi), spill
+constexpr int kBlockStats = 10;
+void launch_row_stats(const RowStatsArgs &a, hipStream_t s);
 // Stable scatter of the rows into their bins.
 void launch_bin_scatter(const int64_t *u, int64_t m, BinEdges be, const int64_t *hist_scan,
                         int64_t nwaves, int32_t *binlist, hipStream_t s);
 void launch_summary(const int64_t *P, int64_t nnzA, const int64_t *cto, int64_t m,
-                    const int64_t *hist_scan, int64_t nwaves, Summary *sum, hipStream_t s);
+                    const int64_t *hist_scan, int64_t nwaves, const int64_t *bpart,
+                    int64_t nblocks, Summary *sum, hipStream_t s);
 
 // ------------------------------------------------------------- compute
 
@@ -136,37 +248,74 @@ int launch_esc(const EscArgs<T> &a, const int32_t *rows, int64_t nrows, int cap,
 
 template <typename T> struct LongArgs {
   EscArgs<T> e;
+  const LongRow *lrows;
   const LongItem *items;
-  const int32_t *work;    // item ids to process
+  const int32_t *work;    // item ids to process (nullptr: all)
   LongState *state;
-  Pool *pool;
+  Pool *pool;             // progressive blocks (spills, one-item rows)
+  Pool *cpool;            // combine outputs
   unsigned int *fail_list;
   int32_t long_slot;
-  int32_t **rsrc_col;     // per row: where the long row's result lives
-  T **rsrc_val;
+  Seq *partials;          // per item (multi-item rows)
+  int32_t *pcol;          // partial buffer
+  T *pval;
+  int32_t *split;         // range starts in every partial
+  Piece *pieces;
+  const int32_t *piece_lrow;
+  LongState *cstate;      // checkpoints of the combine pieces
+  unsigned int *fail_list2;
+  LongCounters *cnt;      // lengths of the two lists below
+  unsigned int *glist;    // items left to the general (multi-tile) kernel
+  unsigned int *glist2;   // pieces left to the general combine kernel
+  int64_t ncols;
 };
 
+// Long-row table, work items and piece map (three launches).
+void launch_long_table(const int32_t *binlist, int64_t off, int64_t nlong, const int64_t *u,
+                       int64_t ncols, LongParams lp, LongRow *lrows, LongItem *items,
+                       LongState *state, Seq *partials, int32_t *piece_lrow, int64_t *tmp,
+                       hipStream_t s);
+void launch_cstate_init(LongState *state, int64_t n, hipStream_t s);
+int combine_maxs();
+int combine_l1cap();
+constexpr int kLongTile = 1024;
+int64_t long_table_tmp_len(int64_t nlong);
+
 template <typename T>
-int launch_long(const LongArgs<T> &a, int64_t nwork, int64_t ncols, int l1cap, hipStream_t s);
+int launch_long(const LongArgs<T> &a, int64_t nwork, int l1cap, hipStream_t s);
+// One-tile fast paths: items / pieces of at most kOneShot entries are sorted
+// and folded in a single pass without the level-1 sequence.
+constexpr int kOneShot = 4096;
+template <typename T> void launch_long_oneshot(const LongArgs<T> &a, int64_t nitems, hipStream_t s);
+template <typename T>
+void launch_combine_oneshot(const LongArgs<T> &a, int64_t npieces, hipStream_t s);
+void launch_item_entry(const int32_t *arp, const int64_t *P, LongItem *items, int64_t n,
+                       hipStream_t s);
+template <typename T>
+int launch_combine(const LongArgs<T> &a, int64_t npieces, hipStream_t s);
 int long_l1cap_default(int dtype_bytes);
-void launch_long_init(const LongItem *items, LongState *state, int64_t n, hipStream_t s);
-void launch_long_items(const int32_t *binlist, int64_t off, int64_t n, const int64_t *u,
-                       LongItem *items, hipStream_t s);
+// Output sizes of the long rows from their pieces: piece scan -> rownnz.
+void launch_long_rownnz(const LongRow *lrows, int64_t nlong, const int64_t *pscan,
+                        int64_t *rownnz, hipStream_t s);
+void scan_piece_counts(const Piece *pieces, int64_t n, int64_t *out, int64_t *part,
+                       hipStream_t s);
 
 template <typename T> struct CompactArgs {
   const int64_t *u;
   const int64_t *cto;
   const int32_t *ct_col;
   const T *ct_val;
-  int32_t *const *rsrc_col;
-  T *const *rsrc_val;
   const int64_t *rowoff;  // exclusive scan of rownnz, m+1
-  int64_t long_min;       // rows with u > long_min take rsrc
+  int64_t long_min;       // rows with u > long_min are copied piece by piece
+  const LongRow *lrows;
+  const Piece *pieces;
+  const int64_t *pscan;   // exclusive scan of the piece sizes
   int32_t *c_rp;
   int32_t *c_col;
   T *c_val;
 };
-template <typename T> void launch_compact(const CompactArgs<T> &a, int64_t m, hipStream_t s);
+template <typename T>
+void launch_compact(const CompactArgs<T> &a, int64_t m, int64_t npieces, hipStream_t s);
 
 void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 
@@ -184,6 +333,7 @@ void launch_grad_b(const int64_t *tptr, const int32_t *trow, const int32_t *tpos
                    const int32_t *brp, const int32_t *bcol, int64_t kb, const int32_t *crp,
                    const int32_t *ccol, const T *dc, T *dB, hipStream_t s);
 void launch_zero(void *p, size_t bytes, hipStream_t s);
+void launch_set_pool(Pool *dst, Pool value, hipStream_t s);
 void launch_status(const int64_t *rowoff, int64_t m, const Pool *pool, ComputeStatus *st,
                    hipStream_t s);
 

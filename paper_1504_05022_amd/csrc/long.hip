@@ -1,11 +1,9 @@
 // Stage 3 for long rows (bin group 5, u > 512 by default): the merge method
-// of Section 3.1.  One work-group owns a work item (a long row, or a range
-// of its products) and inserts its products into a sorted, duplicate-free
-// result sequence:
+// of Section 3.1, split over work-groups.
 //
+// Merge method (one work-group per work item):
 //  * products are taken in expansion order in tiles of TILE; every tile is
-//    sorted on (column, expansion position) and its products are folded per
-//    column;
+//    sorted on (column, position) and its products are folded per column;
 //  * every distinct column of the tile is binary-searched in the level-1
 //    sequence L1 held in LDS: found columns are fused in place (the running
 //    value continues with the tile's products in order), missing ones are
@@ -14,15 +12,26 @@
 //    sequence G (merge path again, fusing columns present in both), which
 //    lives in blocks carved from a device pool and grows 2x at a time
 //    (progressive allocation);
-//  * when the pool is exhausted the item records a checkpoint (the product
-//    position right after its last successful spill, with L1 empty, and G)
-//    and quits; the host grows the pool and relaunches the failed items,
-//    which resume from their checkpoints;
+//  * when the pool is exhausted the item records a checkpoint (the position
+//    right after its last successful spill, with L1 empty, and G) and quits;
+//    the host grows the pool and relaunches the failed items, which resume
+//    from their checkpoints;
 //  * at the end L1 is merged into G once more, or, if G was never used,
-//    written to the row's 256-entry C~ slot or a pool block.
+//    written out directly.
 //
-// Values of items that never spill are Gustavson's sequential sums exactly;
-// spilled items add two partial sums per column (rounding may differ).
+// Splitting (so that rows far longer than the average are balanced):
+//  * phase 1 (k_long): a row is cut into product segments; each segment is
+//    a work item that leaves a sorted, duplicate-free partial.  A row with a
+//    single segment is finished here: its result goes to its 256-entry C~
+//    slot, or to a pool block of 256 * 2^k entries.
+//  * phase 2 (k_combine): for rows with several segments, one work-group per
+//    column range folds that range of every partial, in segment order, into
+//    one output piece with the same merge method.  Phase 1 records where
+//    every range starts in every partial, so phase 2 needs no search.
+//
+// Values of items that neither spill nor are split are Gustavson's
+// sequential sums exactly; otherwise partial sums are added in segment order
+// (rounding may differ, the order is deterministic).
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -122,8 +131,8 @@ DEVI int64_t merge_fuse(const int32_t *xc, const T *xv, int64_t nx, const int32_
   return zo;
 }
 
-// Shared state of a work-group, broadcast through LDS.
-template <typename T> struct LongShared {
+// Work-group state broadcast through LDS.
+template <typename T> struct MergeShared {
   int64_t scan[16];
   int32_t imax[16];
   int32_t *zcol;
@@ -131,6 +140,7 @@ template <typename T> struct LongShared {
   int64_t zcap;
   int32_t ok;
   int32_t next_first;
+  int64_t total;
 };
 
 template <typename T>
@@ -143,21 +153,237 @@ DEVI bool pool_alloc(Pool *pool, uint64_t cap, int32_t *&col, T *&val) {
   return true;
 }
 
+// Sort a tile (keys col << LOGT | position, values pv[position] in LDS),
+// fold every column into L1 (binary-search fuse; new columns are compacted
+// with a prefix sum) and merge the new columns into L1 with merge path.
+// `sk`/`ncol` share LDS region A, `pv`/`nval` region B.  All reads of the
+// tile's staging data must be complete before the call.  Contains barriers.
 template <typename T, int NT, int TILE, int L1CAP, typename Key>
-__global__ __launch_bounds__(NT) void k_long(LongArgs<T> a) {
-  constexpr int KT = TILE / NT;        // products per thread per tile
+DEVI void tile_insert(Key (&key)[TILE / NT], const int tn, Key *sk, T *pv, int32_t *ncol,
+                      T *nval, int32_t *l1c, T *l1v, int &r, const int32_t col_base,
+                      int64_t *scan_smem) {
+  constexpr int KT = TILE / NT;
   constexpr int LOGT = Log2<TILE>::v;
-  constexpr int EO = (L1CAP + NT - 1) / NT;  // L1 entries per thread in the L1 merge
+  constexpr int EO = (L1CAP + NT - 1) / NT;
+  const int t = threadIdx.x;
+  block_bitonic_sort<NT, KT, Key>(key, sk);
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) sk[t * KT + kk] = key[kk];
+  __syncthreads();
+
+  bool isnew[KT];
+  int32_t nc[KT];
+  T nv[KT];
+  int nn = 0;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    isnew[kk] = false;
+    nc[kk] = 0;
+    nv[kk] = T(0);
+    if (l < tn) {
+      const Key c = key[kk] >> LOGT;
+      const bool head = (l == 0) || ((sk[l - 1] >> LOGT) != c);
+      if (head) {
+        const int32_t col = col_base + static_cast<int32_t>(c);
+        int lo = 0, hi = r;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (l1c[mid] < col)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        const bool found = lo < r && l1c[lo] == col;
+        T v = found ? l1v[lo] : T(0);
+        v = v + pv[static_cast<int>(key[kk] & (TILE - 1))];
+        for (int l2 = l + 1; l2 < tn; ++l2) {
+          const Key k2 = sk[l2];
+          if ((k2 >> LOGT) != c) break;
+          v = v + pv[static_cast<int>(k2 & (TILE - 1))];
+        }
+        if (found) {
+          l1v[lo] = v;
+        } else {
+          isnew[kk] = true;
+          nc[kk] = col;
+          nv[kk] = v;
+          ++nn;
+        }
+      }
+    }
+  }
+  int64_t qtot;
+  int o = static_cast<int>(block_excl_sum<NT>(static_cast<int64_t>(nn), scan_smem, qtot));
+  const int q = static_cast<int>(qtot);
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    if (isnew[kk]) {
+      ncol[o] = nc[kk];
+      nval[o] = nv[kk];
+      ++o;
+    }
+  }
+  __syncthreads();
+  if (q > 0) {
+    const int tot = r + q;
+    const int d = t * EO;
+    int32_t oc[EO];
+    T ov[EO];
+    if (d < tot) {
+      int x = split_disjoint(l1c, r, ncol, q, d);
+      int y = d - x;
+#pragma unroll
+      for (int j = 0; j < EO; ++j) {
+        if (d + j < tot) {
+          if (y >= q || (x < r && l1c[x] < ncol[y])) {
+            oc[j] = l1c[x];
+            ov[j] = l1v[x];
+            ++x;
+          } else {
+            oc[j] = ncol[y];
+            ov[j] = nval[y];
+            ++y;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (d < tot) {
+#pragma unroll
+      for (int j = 0; j < EO; ++j) {
+        if (d + j < tot) {
+          l1c[d + j] = oc[j];
+          l1v[d + j] = ov[j];
+        }
+      }
+    }
+    __syncthreads();
+    r = tot;
+  }
+}
+
+// Merge L1 into G (into the spare block if large enough, else a new block of
+// twice G's capacity or more); false if the pool is exhausted (G unchanged).
+template <typename T, int NT>
+DEVI bool spill_l1(LongState &st, int r, const int32_t *l1c, const T *l1v, Pool *pool,
+                   int32_t slot, MergeShared<T> &sh) {
+  const int64_t need = st.gcnt + r;
+  if (threadIdx.x == 0) {
+    sh.ok = 1;
+    if (st.scap >= need) {
+      sh.zcol = st.scol;
+      sh.zval = reinterpret_cast<T *>(st.sval);
+      sh.zcap = st.scap;
+    } else {
+      int64_t cap = st.gcap * 2;
+      if (cap < slot) cap = slot;
+      while (cap < need) cap *= 2;
+      int32_t *zc = nullptr;
+      T *zv = nullptr;
+      if (pool_alloc<T>(pool, static_cast<uint64_t>(cap), zc, zv)) {
+        sh.zcol = zc;
+        sh.zval = zv;
+        sh.zcap = cap;
+      } else {
+        sh.ok = 0;
+      }
+    }
+  }
+  __syncthreads();
+  const bool ok = sh.ok != 0;
+  int32_t *zc = sh.zcol;
+  T *zv = sh.zval;
+  const int64_t zcap = sh.zcap;
+  __syncthreads();
+  if (!ok) return false;
+  const int64_t z = merge_fuse<NT, 8, T>(st.gcol, reinterpret_cast<const T *>(st.gval), st.gcnt,
+                                         l1c, l1v, r, zc, zv, sh.scan);
+  if (st.gcap > 0) {
+    st.scol = st.gcol;
+    st.sval = st.gval;
+    st.scap = st.gcap;
+  } else {
+    st.scol = nullptr;
+    st.sval = nullptr;
+    st.scap = 0;
+  }
+  st.gcol = zc;
+  st.gval = zv;
+  st.gcap = zcap;
+  st.gcnt = z;
+  return true;
+}
+
+// Copy L1 to a destination chosen by thread 0 (`dst` set in sh.zcol/zval).
+template <typename T, int NT>
+DEVI void copy_l1(const int32_t *l1c, const T *l1v, int r, int32_t *dc, T *dv) {
+  for (int x = threadIdx.x; x < r; x += NT) {
+    dc[x] = l1c[x];
+    dv[x] = l1v[x];
+  }
+}
+
+// Record where every combine range starts in a partial held in LDS:
+// pos[b * nseg + s] = first position with column >= b << shift, b = 0..np.
+template <int NT>
+DEVI void split_points_lds(const int32_t *c, int r, int shift, int32_t np, int32_t *pos,
+                           int32_t nseg, int32_t s) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    pos[s] = 0;
+    pos[static_cast<int64_t>(np) * nseg + s] = r;
+  }
+  for (int x = t; x < r; x += NT) {
+    const int32_t b = c[x] >> shift;
+    const int32_t bp = x > 0 ? (c[x - 1] >> shift) : 0;
+    // ranges bp+1 .. b start at x (ranges before the first entry start at 0)
+    for (int32_t q = (x > 0 ? bp + 1 : 1); q <= b && q < np; ++q)
+      pos[static_cast<int64_t>(q) * nseg + s] = x;
+  }
+  // ranges after the last entry start at r
+  if (t == 0) {
+    const int32_t blast = r > 0 ? (c[r - 1] >> shift) : 0;
+    for (int32_t q = (r > 0 ? blast + 1 : 1); q < np; ++q) pos[static_cast<int64_t>(q) * nseg + s] = r;
+  }
+}
+
+// Same for a partial in device memory (after a spill): binary searches.
+template <int NT>
+DEVI void split_points_global(const int32_t *c, int64_t cnt, int shift, int32_t np, int32_t *pos,
+                              int32_t nseg, int32_t s) {
+  for (int32_t b = threadIdx.x; b <= np; b += NT) {
+    int64_t lo = 0, hi = cnt;
+    if (b == np) {
+      lo = cnt;
+    } else {
+      const int32_t key = b << shift;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (c[mid] < key)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+    }
+    pos[static_cast<int64_t>(b) * nseg + s] = static_cast<int32_t>(lo);
+  }
+}
+
+// ------------------------------------------------------------ phase 1
+
+template <typename T, int NT, int TILE, int L1CAP, typename Key>
+DEVI void long_item(LongArgs<T> &a, const int32_t item_id) {
+  constexpr int KT = TILE / NT;
+  constexpr int LOGT = Log2<TILE>::v;
   constexpr Key KMAX = KeyMax<Key>::v;
   constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
 
   __shared__ int32_t l1c[L1CAP];
   __shared__ T l1v[L1CAP];
-  // region A: run starts (int32) / sort scratch and sorted keys / new columns
-  __shared__ __align__(16) unsigned char s_a[TILE * KB];
-  // region B: a_ij of each run / product values / new values
-  __shared__ __align__(16) T s_b[TILE];
-  __shared__ LongShared<T> sh;
+  __shared__ __align__(16) unsigned char s_a[TILE * KB];  // run starts / keys / new columns
+  __shared__ __align__(16) T s_b[TILE];                    // a_ij of runs / products / new values
+  __shared__ MergeShared<T> sh;
 
   int32_t *rs = reinterpret_cast<int32_t *>(s_a);
   Key *sk = reinterpret_cast<Key *>(s_a);
@@ -167,8 +393,8 @@ __global__ __launch_bounds__(NT) void k_long(LongArgs<T> a) {
   T *nval = s_b;
 
   const int t = threadIdx.x;
-  const int32_t item_id = a.work ? a.work[blockIdx.x] : static_cast<int32_t>(blockIdx.x);
   const LongItem item = a.items[item_id];
+  const LongRow lr = a.lrows[item.lrow];
   LongState st = a.state[item_id];
   const int32_t i = item.row;
   const int32_t e0 = a.e.arp[i];
@@ -177,11 +403,11 @@ __global__ __launch_bounds__(NT) void k_long(LongArgs<T> a) {
   const int64_t p1 = item.p1;
   int64_t pos = st.pos;
   int64_t last_clean = pos;
-  int r = 0;  // entries in L1
+  int r = 0;
 
   // entry containing product `pos`: the last e with P[e] <= pbase + pos
   if (t == 0) {
-    int32_t lo = e0, hi = e1;  // search in [e0, e1)
+    int32_t lo = e0, hi = e1;
     while (hi - lo > 1) {
       const int32_t mid = (lo + hi) >> 1;
       if (a.e.P[mid] - pbase <= pos)
@@ -193,61 +419,11 @@ __global__ __launch_bounds__(NT) void k_long(LongArgs<T> a) {
   }
   __syncthreads();
   int32_t e_first = sh.next_first;
-
   bool failed = false;
-
-  // Merge L1 into G (into the spare block or a new 2x block); false if the
-  // pool is exhausted (G unchanged).
-  auto spill = [&]() -> bool {
-    const int64_t need = st.gcnt + r;
-    if (t == 0) {
-      sh.ok = 1;
-      if (st.scap >= need) {
-        sh.zcol = st.scol;
-        sh.zval = reinterpret_cast<T *>(st.sval);
-        sh.zcap = st.scap;
-      } else {
-        int64_t cap = st.gcap * 2;
-        if (cap < a.long_slot) cap = a.long_slot;
-        while (cap < need) cap *= 2;
-        int32_t *zc = nullptr;
-        T *zv = nullptr;
-        if (pool_alloc<T>(a.pool, static_cast<uint64_t>(cap), zc, zv)) {
-          sh.zcol = zc;
-          sh.zval = zv;
-          sh.zcap = cap;
-        } else {
-          sh.ok = 0;
-        }
-      }
-    }
-    __syncthreads();
-    if (!sh.ok) return false;
-    int32_t *zc = sh.zcol;
-    T *zv = sh.zval;
-    const int64_t zcap = sh.zcap;
-    const int64_t z = merge_fuse<NT, 8, T>(st.gcol, reinterpret_cast<const T *>(st.gval),
-                                           st.gcnt, l1c, l1v, r, zc, zv, sh.scan);
-    // the old G becomes the spare block
-    if (st.gcap > 0) {
-      st.scol = st.gcol;
-      st.sval = st.gval;
-      st.scap = st.gcap;
-    } else {
-      st.scol = nullptr;
-      st.sval = nullptr;
-      st.scap = 0;
-    }
-    st.gcol = zc;
-    st.gval = zv;
-    st.gcap = zcap;
-    st.gcnt = z;
-    return true;
-  };
 
   while (pos < p1) {
     if (r + TILE > L1CAP) {
-      if (!spill()) {
+      if (!spill_l1<T, NT>(st, r, l1c, l1v, a.pool, a.long_slot, sh)) {
         failed = true;
         break;
       }
@@ -256,7 +432,7 @@ __global__ __launch_bounds__(NT) void k_long(LongArgs<T> a) {
     }
     const int tn = static_cast<int>(p1 - pos < TILE ? p1 - pos : TILE);
 
-    // ---- expansion: run starts of the entries overlapping [pos, pos+tn)
+    // run starts of the entries overlapping [pos, pos+tn)
 #pragma unroll
     for (int kk = 0; kk < KT; ++kk) rs[t * KT + kk] = -1;
     if (t == 0) sh.next_first = e_first;
@@ -308,122 +484,30 @@ __global__ __launch_bounds__(NT) void k_long(LongArgs<T> a) {
         key[kk] = (static_cast<Key>(c) << LOGT) | static_cast<Key>(l);
       }
     }
-    __syncthreads();  // all reads of rs / ra done
+    __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < KT; ++kk) {
       const int l = t * KT + kk;
       if (l < tn) pv[l] = prod[kk];
     }
-    block_bitonic_sort<NT, KT, Key>(key, sk);
-#pragma unroll
-    for (int kk = 0; kk < KT; ++kk) sk[t * KT + kk] = key[kk];
-    __syncthreads();
-
-    // ---- fold every column of the tile, continuing L1's running value
-    bool isnew[KT];
-    int32_t nc[KT];
-    T nv[KT];
-    int nn = 0;
-#pragma unroll
-    for (int kk = 0; kk < KT; ++kk) {
-      const int l = t * KT + kk;
-      isnew[kk] = false;
-      nc[kk] = 0;
-      nv[kk] = T(0);
-      if (l < tn) {
-        const Key c = key[kk] >> LOGT;
-        const bool head = (l == 0) || ((sk[l - 1] >> LOGT) != c);
-        if (head) {
-          const int32_t col = static_cast<int32_t>(c);
-          int lo = 0, hi = r;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (l1c[mid] < col)
-              lo = mid + 1;
-            else
-              hi = mid;
-          }
-          const bool found = lo < r && l1c[lo] == col;
-          T v = found ? l1v[lo] : T(0);
-          v = v + pv[static_cast<int>(key[kk] & (TILE - 1))];
-          for (int l2 = l + 1; l2 < tn; ++l2) {
-            const Key k2 = sk[l2];
-            if ((k2 >> LOGT) != c) break;
-            v = v + pv[static_cast<int>(k2 & (TILE - 1))];
-          }
-          if (found) {
-            l1v[lo] = v;
-          } else {
-            isnew[kk] = true;
-            nc[kk] = col;
-            nv[kk] = v;
-            ++nn;
-          }
-        }
-      }
-    }
-    int64_t qtot;
-    int o = static_cast<int>(block_excl_sum<NT>(static_cast<int64_t>(nn), sh.scan, qtot));
-    const int q = static_cast<int>(qtot);
-#pragma unroll
-    for (int kk = 0; kk < KT; ++kk) {
-      if (isnew[kk]) {
-        ncol[o] = nc[kk];
-        nval[o] = nv[kk];
-        ++o;
-      }
-    }
-    __syncthreads();
-
-    // ---- merge path of L1 (r) and the new columns (q) back into L1
-    if (q > 0) {
-      const int tot = r + q;
-      const int d = t * EO;
-      int32_t oc[EO];
-      T ov[EO];
-      if (d < tot) {
-        int x = split_disjoint(l1c, r, ncol, q, d);
-        int y = d - x;
-#pragma unroll
-        for (int j = 0; j < EO; ++j) {
-          if (d + j < tot) {
-            if (y >= q || (x < r && l1c[x] < ncol[y])) {
-              oc[j] = l1c[x];
-              ov[j] = l1v[x];
-              ++x;
-            } else {
-              oc[j] = ncol[y];
-              ov[j] = nval[y];
-              ++y;
-            }
-          }
-        }
-      }
-      __syncthreads();
-      if (d < tot) {
-#pragma unroll
-        for (int j = 0; j < EO; ++j) {
-          if (d + j < tot) {
-            l1c[d + j] = oc[j];
-            l1v[d + j] = ov[j];
-          }
-        }
-      }
-      __syncthreads();
-      r = tot;
-    }
+    tile_insert<T, NT, TILE, L1CAP, Key>(key, tn, sk, pv, ncol, nval, l1c, l1v, r, 0, sh.scan);
     pos += tn;
   }
 
-  // ---- final placement of the result
+  const bool single = lr.nseg <= 1;
   int32_t *dcol = nullptr;
   T *dval = nullptr;
   int64_t cnt = 0;
+  bool in_lds = false;
   if (!failed) {
     if (st.gcnt == 0) {
+      // the whole result is in L1
       if (t == 0) {
         sh.ok = 1;
-        if (r <= a.long_slot && item.part == 0 && item.p0 == 0 && item.p1 == a.e.u[i]) {
+        if (!single) {
+          sh.zcol = a.pcol + lr.pbase + item.p0;
+          sh.zval = a.pval + lr.pbase + item.p0;
+        } else if (r <= a.long_slot) {
           sh.zcol = a.e.ct_col + a.e.cto[i];
           sh.zval = a.e.ct_val + a.e.cto[i];
         } else {
@@ -443,16 +527,14 @@ __global__ __launch_bounds__(NT) void k_long(LongArgs<T> a) {
       if (sh.ok) {
         dcol = sh.zcol;
         dval = sh.zval;
-        for (int x = t; x < r; x += NT) {
-          dcol[x] = l1c[x];
-          dval[x] = l1v[x];
-        }
+        copy_l1<T, NT>(l1c, l1v, r, dcol, dval);
         cnt = r;
+        in_lds = true;
       } else {
         failed = true;
       }
     } else {
-      if (r > 0 && !spill()) {
+      if (r > 0 && !spill_l1<T, NT>(st, r, l1c, l1v, a.pool, a.long_slot, sh)) {
         failed = true;
       } else {
         dcol = st.gcol;
@@ -463,8 +545,6 @@ __global__ __launch_bounds__(NT) void k_long(LongArgs<T> a) {
   }
 
   if (failed) {
-    // checkpoint: resume at the last position where L1 was empty, with G as
-    // it was then (G only changes in a successful spill)
     if (t == 0) {
       st.pos = last_clean;
       st.status = 1;
@@ -474,22 +554,756 @@ __global__ __launch_bounds__(NT) void k_long(LongArgs<T> a) {
     }
     return;
   }
+  if (!single) {
+    // where every combine range starts in this partial
+    const int32_t s = static_cast<int32_t>(item_id - lr.item0);
+    int32_t *pos_tab = a.split + lr.sbase;
+    if (in_lds)
+      split_points_lds<NT>(l1c, r, lr.shift, lr.npiece, pos_tab, lr.nseg, s);
+    else
+      split_points_global<NT>(dcol, cnt, lr.shift, lr.npiece, pos_tab, lr.nseg, s);
+  }
   if (t == 0) {
     st.pos = p1;
     st.status = 0;
     a.state[item_id] = st;
-    a.e.rownnz[i] = cnt;
-    a.rsrc_col[i] = dcol;
-    a.rsrc_val[i] = dval;
+    if (single) {
+      Piece pc;
+      pc.col = dcol;
+      pc.val = dval;
+      pc.cnt = cnt;
+      pc.lrow = item.lrow;
+      pc.pad = 0;
+      a.pieces[lr.piece0] = pc;
+    } else {
+      Seq q;
+      q.col = dcol;
+      q.val = dval;
+      q.cnt = cnt;
+      a.partials[item_id] = q;
+    }
   }
 }
 
-// Initial checkpoints: every item starts at its first product with empty G.
-__global__ void k_long_init(const LongItem *items, LongState *state, int64_t n) {
+// ------------------------------------------------------------ phase 2
+
+// One work-group per output piece of a multi-segment row: entries of the
+// piece's column range from all partials, in segment order, through the
+// merge method.  Pieces of one-segment rows are skipped (phase 1 wrote them).
+template <typename T, int NT, int TILE, int L1CAP, typename Key, int MAXS>
+DEVI void combine_piece(LongArgs<T> &a, const int32_t pid) {
+  constexpr int KT = TILE / NT;
+  constexpr int LOGT = Log2<TILE>::v;
+  constexpr Key KMAX = KeyMax<Key>::v;
+  constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
+
+  __shared__ int32_t l1c[L1CAP];
+  __shared__ T l1v[L1CAP];
+  __shared__ __align__(16) unsigned char s_a[TILE * KB];
+  __shared__ __align__(16) T s_b[TILE];
+  __shared__ int32_t sg_off[MAXS + 1];  // first entry of segment s in this piece's stream
+  __shared__ int32_t sg_lo[MAXS];       // start of the range in partial s
+  __shared__ const int32_t *sg_col[MAXS];
+  __shared__ const T *sg_val[MAXS];
+  __shared__ MergeShared<T> sh;
+
+  Key *sk = reinterpret_cast<Key *>(s_a);
+  int32_t *ncol = reinterpret_cast<int32_t *>(s_a);
+  T *pv = s_b;
+  T *nval = s_b;
+
+  const int t = threadIdx.x;
+  const int32_t lri = a.piece_lrow[pid];
+  const LongRow lr = a.lrows[lri];
+  if (lr.nseg <= 1) return;  // uniform across the block
+  LongState st = a.cstate[pid];
+  const int32_t b = static_cast<int32_t>(pid - lr.piece0);
+  const int32_t c0 = b << lr.shift;
+  const int32_t nseg = lr.nseg;
+  const int32_t *pos_tab = a.split + lr.sbase;
+
+  // segment table and the stream length
+  int64_t carry = 0;
+  for (int32_t s0 = 0; s0 < nseg; s0 += NT) {
+    const int32_t s = s0 + t;
+    int64_t len = 0;
+    if (s < nseg) {
+      const Seq q = a.partials[lr.item0 + s];
+      int64_t lo = 0, hi = 0;
+      if (q.cnt > 0 && q.col != nullptr) {
+        // range starts were recorded by the item that produced the partial;
+        // clamped so that a partial that is not there reads nothing
+        lo = pos_tab[static_cast<int64_t>(b) * nseg + s];
+        hi = pos_tab[static_cast<int64_t>(b + 1) * nseg + s];
+        lo = lo < 0 ? 0 : (lo > q.cnt ? q.cnt : lo);
+        hi = hi < lo ? lo : (hi > q.cnt ? q.cnt : hi);
+      }
+      sg_lo[s] = static_cast<int32_t>(lo);
+      sg_col[s] = q.col;
+      sg_val[s] = reinterpret_cast<const T *>(q.val);
+      len = hi - lo;
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_sum<NT>(len, sh.scan, tot);
+    if (s < nseg) sg_off[s] = static_cast<int32_t>(carry + ex);
+    carry += tot;
+  }
+  if (t == 0) sg_off[nseg] = static_cast<int32_t>(carry);
+  __syncthreads();
+  const int64_t E = carry;
+  int64_t pos = st.pos;
+  int64_t last_clean = pos;
+  int r = 0;
+  bool failed = false;
+
+  while (pos < E) {
+    if (r + TILE > L1CAP) {
+      if (!spill_l1<T, NT>(st, r, l1c, l1v, a.pool, a.long_slot, sh)) {
+        failed = true;
+        break;
+      }
+      r = 0;
+      last_clean = pos;
+    }
+    const int tn = static_cast<int>(E - pos < TILE ? E - pos : TILE);
+    Key key[KT];
+    T val[KT];
+    {
+      // segment of this thread's first entry, then walk forward
+      const int64_t g0 = pos + t * KT;
+      int lo = 0, hi = nseg;  // last s with sg_off[s] <= g0
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sg_off[mid] <= g0)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      int s = lo;
+#pragma unroll
+      for (int kk = 0; kk < KT; ++kk) {
+        const int l = t * KT + kk;
+        key[kk] = KMAX;
+        val[kk] = T(0);
+        if (l < tn) {
+          const int64_t g = pos + l;
+          while (s + 1 < nseg && sg_off[s + 1] <= g) ++s;
+          const int64_t idx = sg_lo[s] + (g - sg_off[s]);
+          const int32_t c = sg_col[s][idx];
+          val[kk] = sg_val[s][idx];
+          key[kk] = (static_cast<Key>(c - c0) << LOGT) | static_cast<Key>(l);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KT; ++kk) {
+      const int l = t * KT + kk;
+      if (l < tn) pv[l] = val[kk];
+    }
+    tile_insert<T, NT, TILE, L1CAP, Key>(key, tn, sk, pv, ncol, nval, l1c, l1v, r, c0, sh.scan);
+    pos += tn;
+  }
+
+  int32_t *dcol = nullptr;
+  T *dval = nullptr;
+  int64_t cnt = 0;
+  if (!failed) {
+    if (st.gcnt == 0) {
+      if (t == 0) {
+        sh.ok = 1;
+        int32_t *zc = nullptr;
+        T *zv = nullptr;
+        if (r == 0) {
+          sh.zcol = nullptr;
+          sh.zval = nullptr;
+        } else if (pool_alloc<T>(a.pool, static_cast<uint64_t>(r), zc, zv)) {
+          sh.zcol = zc;
+          sh.zval = zv;
+        } else {
+          sh.ok = 0;
+        }
+      }
+      __syncthreads();
+      if (sh.ok) {
+        dcol = sh.zcol;
+        dval = sh.zval;
+        if (r > 0) copy_l1<T, NT>(l1c, l1v, r, dcol, dval);
+        cnt = r;
+      } else {
+        failed = true;
+      }
+    } else {
+      if (r > 0 && !spill_l1<T, NT>(st, r, l1c, l1v, a.pool, a.long_slot, sh)) {
+        failed = true;
+      } else {
+        dcol = st.gcol;
+        dval = reinterpret_cast<T *>(st.gval);
+        cnt = st.gcnt;
+      }
+    }
+  }
+  if (failed) {
+    if (t == 0) {
+      st.pos = last_clean;
+      st.status = 1;
+      a.cstate[pid] = st;
+      const unsigned int k = atomicAdd(&a.pool->fail2, 1u);
+      a.fail_list2[k] = static_cast<unsigned int>(pid);
+    }
+    return;
+  }
+  if (t == 0) {
+    st.pos = E;
+    st.status = 0;
+    a.cstate[pid] = st;
+    Piece pc;
+    pc.col = dcol;
+    pc.val = dval;
+    pc.cnt = cnt;
+    pc.lrow = lri;
+    pc.pad = 0;
+    a.pieces[pid] = pc;
+  }
+}
+
+// General kernels: an explicit work list (relaunch after pool exhaustion),
+// or the work the one-tile kernels left behind, in a grid-stride loop.
+template <typename T, int NT, int TILE, int L1CAP, typename Key>
+__global__ __launch_bounds__(NT) void k_long(LongArgs<T> a) {
+  if (a.work) {
+    long_item<T, NT, TILE, L1CAP, Key>(a, a.work[blockIdx.x]);
+    return;
+  }
+  const unsigned int n = a.cnt->glong;
+  for (unsigned int w = blockIdx.x; w < n; w += gridDim.x) {
+    __syncthreads();
+    long_item<T, NT, TILE, L1CAP, Key>(a, static_cast<int32_t>(a.glist[w]));
+  }
+}
+
+template <typename T, int NT, int TILE, int L1CAP, typename Key, int MAXS>
+__global__ __launch_bounds__(NT) void k_combine(LongArgs<T> a) {
+  if (a.work) {
+    combine_piece<T, NT, TILE, L1CAP, Key, MAXS>(a, a.work[blockIdx.x]);
+    return;
+  }
+  const unsigned int n = a.cnt->gcomb;
+  for (unsigned int w = blockIdx.x; w < n; w += gridDim.x) {
+    __syncthreads();
+    combine_piece<T, NT, TILE, L1CAP, Key, MAXS>(a, static_cast<int32_t>(a.glist2[w]));
+  }
+}
+
+// ------------------------------------------------------- one-tile paths
+// An item (or a combine piece) with at most TILE entries needs no level-1
+// sequence: all its products are sorted at once, folded, and written
+// straight to their destination.  Anything larger, and any item whose
+// destination block cannot be allocated, is left to the general kernel.
+
+// Output of a one-tile pass: head flags and the running output index.
+// Writes the range starts of a multi-segment row's partial from the heads.
+template <typename Key, int KT, int LOGT>
+DEVI void oneshot_split_points(const Key (&key)[KT], const bool (&hd)[KT], const int32_t (&ho)[KT],
+                               const Key *sk, int tn, int r, int32_t col_base, int shift,
+                               int32_t np, int32_t *pos, int32_t nseg, int32_t s) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    if (l < tn && hd[kk]) {
+      const int32_t c = col_base + static_cast<int32_t>(key[kk] >> LOGT);
+      const int32_t b = c >> shift;
+      const int32_t bp =
+          l > 0 ? ((col_base + static_cast<int32_t>(sk[l - 1] >> LOGT)) >> shift) : -1;
+      for (int32_t q = bp + 1; q <= b && q < np; ++q)
+        pos[static_cast<int64_t>(q) * nseg + s] = ho[kk];
+    }
+    if (l == tn - 1) {
+      const int32_t c = col_base + static_cast<int32_t>(key[kk] >> LOGT);
+      for (int32_t q = (c >> shift) + 1; q < np; ++q) pos[static_cast<int64_t>(q) * nseg + s] = r;
+      pos[static_cast<int64_t>(np) * nseg + s] = r;
+    }
+  }
+}
+
+template <typename T, int NT, int TILE, typename Key>
+__global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
+  constexpr int KT = TILE / NT;
+  constexpr int LOGT = Log2<TILE>::v;
+  constexpr Key KMAX = KeyMax<Key>::v;
+  constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
+  __shared__ __align__(16) unsigned char s_a[TILE * KB];  // run starts / keys
+  __shared__ __align__(16) T s_b[TILE];                    // a_ij of runs / products
+  __shared__ MergeShared<T> sh;
+  int32_t *rs = reinterpret_cast<int32_t *>(s_a);
+  Key *sk = reinterpret_cast<Key *>(s_a);
+  T *ra = s_b;
+  T *pv = s_b;
+
+  const int t = threadIdx.x;
+  const int32_t item_id = static_cast<int32_t>(blockIdx.x);
+  const LongItem item = a.items[item_id];
+  const int64_t p0 = item.p0, p1 = item.p1;
+  if (p1 - p0 > TILE) {
+    if (t == 0) a.glist[atomicAdd(&a.cnt->glong, 1u)] = static_cast<unsigned int>(item_id);
+    return;
+  }
+  const LongRow lr = a.lrows[item.lrow];
+  const int32_t i = item.row;
+  const int32_t e1 = a.e.arp[i + 1];
+  const int64_t pbase = a.e.P[a.e.arp[i]];
+  const int tn = static_cast<int>(p1 - p0);
+
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) rs[t * KT + kk] = -1;
+  __syncthreads();
+  for (int32_t e = item.e_first + t; e < e1; e += NT) {
+    const int64_t s0 = a.e.P[e] - pbase;
+    if (s0 >= p1) break;
+    const int64_t s1 = a.e.P[e + 1] - pbase;
+    if (s1 > p0 && s1 > s0) {
+      int64_t ls = s0 - p0;
+      int32_t off = 0;
+      if (ls < 0) {
+        off = static_cast<int32_t>(-ls);
+        ls = 0;
+      }
+      rs[ls] = a.e.brp[a.e.acol[e]] + off;
+      ra[ls] = a.e.aval[e];
+    }
+  }
+  __syncthreads();
+  int st_run[KT];
+  int run = -1;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    const int f = (l < tn && rs[l] >= 0) ? l : -1;
+    run = max(run, f);
+    st_run[kk] = run;
+  }
+  const int before = block_excl_max<NT>(run, sh.imax);
+  Key key[KT];
+  T prod[KT];
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    key[kk] = KMAX;
+    prod[kk] = T(0);
+    const int s0 = max(before, st_run[kk]);
+    if (l < tn && s0 >= 0) {
+      const int32_t bidx = rs[s0] + (l - s0);
+      const T av = ra[s0];
+      const int32_t c = a.e.bcol[bidx];
+      prod[kk] = av * a.e.bval[bidx];
+      key[kk] = (static_cast<Key>(c) << LOGT) | static_cast<Key>(l);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    if (l < tn) pv[l] = prod[kk];
+  }
+  block_bitonic_sort<NT, KT, Key>(key, sk);
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) sk[t * KT + kk] = key[kk];
+  __syncthreads();
+
+  bool hd[KT];
+  int nh = 0;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    hd[kk] = l < tn && (l == 0 || (sk[l - 1] >> LOGT) != (key[kk] >> LOGT));
+    nh += hd[kk] ? 1 : 0;
+  }
+  int64_t rtot;
+  int o = static_cast<int>(block_excl_sum<NT>(static_cast<int64_t>(nh), sh.scan, rtot));
+  const int r = static_cast<int>(rtot);
+  const bool single = lr.nseg <= 1;
+  if (t == 0) {
+    sh.ok = 1;
+    if (!single) {
+      sh.zcol = a.pcol + lr.pbase + p0;
+      sh.zval = a.pval + lr.pbase + p0;
+    } else if (r <= a.long_slot) {
+      sh.zcol = a.e.ct_col + a.e.cto[i];
+      sh.zval = a.e.ct_val + a.e.cto[i];
+    } else {
+      int64_t cap = a.long_slot;
+      while (cap < r) cap *= 2;
+      int32_t *zc = nullptr;
+      T *zv = nullptr;
+      if (pool_alloc<T>(a.pool, static_cast<uint64_t>(cap), zc, zv)) {
+        sh.zcol = zc;
+        sh.zval = zv;
+      } else {
+        sh.ok = 0;
+      }
+    }
+  }
+  __syncthreads();
+  if (!sh.ok) {
+    // left to the general kernel, which can record a checkpoint
+    if (t == 0) a.glist[atomicAdd(&a.cnt->glong, 1u)] = static_cast<unsigned int>(item_id);
+    return;
+  }
+  int32_t *dcol = sh.zcol;
+  T *dval = sh.zval;
+  int32_t ho[KT];
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    ho[kk] = o;
+    if (hd[kk]) {
+      const Key c = key[kk] >> LOGT;
+      T v = T(0);
+      v = v + pv[static_cast<int>(key[kk] & (TILE - 1))];
+      for (int l2 = l + 1; l2 < tn; ++l2) {
+        const Key k2 = sk[l2];
+        if ((k2 >> LOGT) != c) break;
+        v = v + pv[static_cast<int>(k2 & (TILE - 1))];
+      }
+      dcol[o] = static_cast<int32_t>(c);
+      dval[o] = v;
+      ++o;
+    }
+  }
+  if (!single)
+    oneshot_split_points<Key, KT, LOGT>(key, hd, ho, sk, tn, r, 0, lr.shift, lr.npiece,
+                                        a.split + lr.sbase, lr.nseg,
+                                        static_cast<int32_t>(item_id - lr.item0));
+  if (t == 0) {
+    LongState st = a.state[item_id];
+    st.pos = p1;
+    st.status = 0;
+    a.state[item_id] = st;
+    if (single) {
+      Piece pc;
+      pc.col = dcol;
+      pc.val = dval;
+      pc.cnt = r;
+      pc.lrow = item.lrow;
+      pc.pad = 0;
+      a.pieces[lr.piece0] = pc;
+    } else {
+      Seq q;
+      q.col = dcol;
+      q.val = dval;
+      q.cnt = r;
+      a.partials[item_id] = q;
+    }
+  }
+}
+
+template <typename T, int NT, int TILE, typename Key, int MAXS>
+__global__ __launch_bounds__(NT) void k_combine1(LongArgs<T> a) {
+  constexpr int KT = TILE / NT;
+  constexpr int LOGT = Log2<TILE>::v;
+  constexpr Key KMAX = KeyMax<Key>::v;
+  constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
+  __shared__ __align__(16) unsigned char s_a[TILE * KB];
+  __shared__ __align__(16) T s_b[TILE];
+  __shared__ int32_t sg_off[MAXS + 1];
+  __shared__ int32_t sg_lo[MAXS];
+  __shared__ const int32_t *sg_col[MAXS];
+  __shared__ const T *sg_val[MAXS];
+  __shared__ MergeShared<T> sh;
+  Key *sk = reinterpret_cast<Key *>(s_a);
+  T *pv = s_b;
+
+  const int t = threadIdx.x;
+  const int32_t pid = static_cast<int32_t>(blockIdx.x);
+  const int32_t lri = a.piece_lrow[pid];
+  const LongRow lr = a.lrows[lri];
+  if (lr.nseg <= 1) return;
+  const int32_t b = static_cast<int32_t>(pid - lr.piece0);
+  const int32_t c0 = b << lr.shift;
+  const int32_t nseg = lr.nseg;
+  const int32_t *pos_tab = a.split + lr.sbase;
+  int64_t carry = 0;
+  for (int32_t s0 = 0; s0 < nseg; s0 += NT) {
+    const int32_t s = s0 + t;
+    int64_t len = 0;
+    if (s < nseg) {
+      const Seq q = a.partials[lr.item0 + s];
+      int64_t lo = 0, hi = 0;
+      if (q.cnt > 0 && q.col != nullptr) {
+        lo = pos_tab[static_cast<int64_t>(b) * nseg + s];
+        hi = pos_tab[static_cast<int64_t>(b + 1) * nseg + s];
+        lo = lo < 0 ? 0 : (lo > q.cnt ? q.cnt : lo);
+        hi = hi < lo ? lo : (hi > q.cnt ? q.cnt : hi);
+      }
+      sg_lo[s] = static_cast<int32_t>(lo);
+      sg_col[s] = q.col;
+      sg_val[s] = reinterpret_cast<const T *>(q.val);
+      len = hi - lo;
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_sum<NT>(len, sh.scan, tot);
+    if (s < nseg) sg_off[s] = static_cast<int32_t>(carry + ex);
+    carry += tot;
+  }
+  if (t == 0) sg_off[nseg] = static_cast<int32_t>(carry);
+  __syncthreads();
+  const int64_t E = carry;
+  if (E > TILE) {
+    if (t == 0) a.glist2[atomicAdd(&a.cnt->gcomb, 1u)] = static_cast<unsigned int>(pid);
+    return;
+  }
+  const int tn = static_cast<int>(E);
+  Key key[KT];
+  T val[KT];
+  {
+    const int g0 = t * KT;
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (sg_off[mid] <= g0)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    int s = lo;
+#pragma unroll
+    for (int kk = 0; kk < KT; ++kk) {
+      const int l = t * KT + kk;
+      key[kk] = KMAX;
+      val[kk] = T(0);
+      if (l < tn) {
+        while (s + 1 < nseg && sg_off[s + 1] <= l) ++s;
+        const int64_t idx = sg_lo[s] + (l - sg_off[s]);
+        const int32_t c = sg_col[s][idx];
+        val[kk] = sg_val[s][idx];
+        key[kk] = (static_cast<Key>(c - c0) << LOGT) | static_cast<Key>(l);
+      }
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    if (l < tn) pv[l] = val[kk];
+  }
+  block_bitonic_sort<NT, KT, Key>(key, sk);
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) sk[t * KT + kk] = key[kk];
+  __syncthreads();
+  bool hd[KT];
+  int nh = 0;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    hd[kk] = l < tn && (l == 0 || (sk[l - 1] >> LOGT) != (key[kk] >> LOGT));
+    nh += hd[kk] ? 1 : 0;
+  }
+  int64_t rtot;
+  int o = static_cast<int>(block_excl_sum<NT>(static_cast<int64_t>(nh), sh.scan, rtot));
+  const int r = static_cast<int>(rtot);
+  if (t == 0) {
+    sh.ok = 1;
+    int32_t *zc = nullptr;
+    T *zv = nullptr;
+    if (r == 0) {
+      sh.zcol = nullptr;
+      sh.zval = nullptr;
+    } else if (pool_alloc<T>(a.pool, static_cast<uint64_t>(r), zc, zv)) {
+      sh.zcol = zc;
+      sh.zval = zv;
+    } else {
+      sh.ok = 0;
+    }
+  }
+  __syncthreads();
+  if (!sh.ok) {
+    if (t == 0) a.glist2[atomicAdd(&a.cnt->gcomb, 1u)] = static_cast<unsigned int>(pid);
+    return;
+  }
+  int32_t *dcol = sh.zcol;
+  T *dval = sh.zval;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    if (hd[kk]) {
+      const Key c = key[kk] >> LOGT;
+      T v = T(0);
+      v = v + pv[static_cast<int>(key[kk] & (TILE - 1))];
+      for (int l2 = l + 1; l2 < tn; ++l2) {
+        const Key k2 = sk[l2];
+        if ((k2 >> LOGT) != c) break;
+        v = v + pv[static_cast<int>(k2 & (TILE - 1))];
+      }
+      dcol[o] = c0 + static_cast<int32_t>(c);
+      dval[o] = v;
+      ++o;
+    }
+  }
+  if (t == 0) {
+    LongState st = a.cstate[pid];
+    st.pos = E;
+    a.cstate[pid] = st;
+    Piece pc;
+    pc.col = dcol;
+    pc.val = dval;
+    pc.cnt = r;
+    pc.lrow = lri;
+    pc.pad = 0;
+    a.pieces[pid] = pc;
+  }
+}
+
+// Entry of A's row that contains the first product of every item.
+__global__ void k_item_entry(const int32_t *arp, const int64_t *P, LongItem *items, int64_t n) {
+  const int64_t x = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  LongItem it = items[x];
+  const int32_t e0 = arp[it.row], e1 = arp[it.row + 1];
+  const int64_t pbase = P[e0];
+  int32_t lo = e0, hi = e1;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (P[mid] - pbase <= it.p0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  items[x].e_first = lo;
+}
+
+void launch_item_entry(const int32_t *arp, const int64_t *P, LongItem *items, int64_t n,
+                       hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_item_entry, dim3((n + 255) / 256), dim3(256), 0, s, arp, P, items, n);
+}
+
+// ------------------------------------------------------------ long table
+
+int64_t long_table_tmp_len(int64_t nlong) { return 4 * ((nlong + 255) / 256 + 1); }
+
+struct LtSums {
+  int64_t items, pieces, umulti, split;
+};
+
+DEVI LtSums lt_plan(const int32_t *binlist, int64_t off, int64_t t, int64_t nlong,
+                    const int64_t *u, int64_t ncols, const LongParams &lp, LongRow &lr) {
+  LtSums z{0, 0, 0, 0};
+  if (t >= nlong) return z;
+  const int32_t row = binlist[off + t];
+  const int64_t ui = u[row];
+  int64_t segp;
+  int32_t nseg, shift, npiece;
+  long_row_plan(ui, ncols, lp, segp, nseg, shift, npiece);
+  lr.row = row;
+  lr.nseg = nseg;
+  lr.npiece = npiece;
+  lr.shift = shift;
+  lr.u = ui;
+  lr.segp = segp;
+  z.items = nseg;
+  z.pieces = npiece;
+  z.umulti = nseg > 1 ? ui : 0;
+  z.split = nseg > 1 ? static_cast<int64_t>(nseg) * (npiece + 1) : 0;
+  return z;
+}
+
+__global__ __launch_bounds__(256) void k_lt_reduce(const int32_t *binlist, int64_t off,
+                                                   int64_t nlong, const int64_t *u,
+                                                   int64_t ncols, LongParams lp, int64_t *tmp) {
+  __shared__ int64_t sm[256 / WAVE + 1];
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  LongRow lr;
+  const LtSums z = lt_plan(binlist, off, t, nlong, u, ncols, lp, lr);
+  int64_t tot;
+  block_excl_sum<256>(z.items, sm, tot);
+  if (threadIdx.x == 0) tmp[4 * blockIdx.x + 0] = tot;
+  block_excl_sum<256>(z.pieces, sm, tot);
+  if (threadIdx.x == 0) tmp[4 * blockIdx.x + 1] = tot;
+  block_excl_sum<256>(z.umulti, sm, tot);
+  if (threadIdx.x == 0) tmp[4 * blockIdx.x + 2] = tot;
+  block_excl_sum<256>(z.split, sm, tot);
+  if (threadIdx.x == 0) tmp[4 * blockIdx.x + 3] = tot;
+}
+
+__global__ void k_lt_scan(int64_t *tmp, int64_t nb) {
+  const int c = threadIdx.x;
+  if (c >= 4) return;
+  int64_t run = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t v = tmp[4 * b + c];
+    tmp[4 * b + c] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lt_write(const int32_t *binlist, int64_t off,
+                                                  int64_t nlong, const int64_t *u, int64_t ncols,
+                                                  LongParams lp, const int64_t *tmp,
+                                                  LongRow *lrows, LongItem *items,
+                                                  LongState *state, Seq *partials,
+                                                  int32_t *piece_lrow) {
+  __shared__ int64_t sm[256 / WAVE + 1];
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  LongRow lr;
+  const LtSums z = lt_plan(binlist, off, t, nlong, u, ncols, lp, lr);
+  int64_t tot;
+  const int64_t i0 = block_excl_sum<256>(z.items, sm, tot) + tmp[4 * blockIdx.x + 0];
+  const int64_t p0 = block_excl_sum<256>(z.pieces, sm, tot) + tmp[4 * blockIdx.x + 1];
+  const int64_t u0 = block_excl_sum<256>(z.umulti, sm, tot) + tmp[4 * blockIdx.x + 2];
+  const int64_t s0 = block_excl_sum<256>(z.split, sm, tot) + tmp[4 * blockIdx.x + 3];
+  if (t >= nlong) return;
+  lr.item0 = i0;
+  lr.piece0 = p0;
+  lr.pbase = u0;
+  lr.sbase = s0;
+  lrows[t] = lr;
+  for (int32_t s = 0; s < lr.nseg; ++s) {
+    LongItem it;
+    it.row = lr.row;
+    it.lrow = static_cast<int32_t>(t);
+    it.p0 = static_cast<int64_t>(s) * lr.segp;
+    it.p1 = it.p0 + lr.segp < lr.u ? it.p0 + lr.segp : lr.u;
+    items[i0 + s] = it;
+    LongState st;
+    st.pos = it.p0;
+    st.gcnt = 0;
+    st.gcap = 0;
+    st.gcol = nullptr;
+    st.gval = nullptr;
+    st.scap = 0;
+    st.scol = nullptr;
+    st.sval = nullptr;
+    st.status = 0;
+    st.pad = 0;
+    state[i0 + s] = st;
+    Seq q;
+    q.col = nullptr;
+    q.val = nullptr;
+    q.cnt = 0;
+    partials[i0 + s] = q;
+  }
+  for (int32_t q = 0; q < lr.npiece; ++q) piece_lrow[p0 + q] = static_cast<int32_t>(t);
+}
+
+void launch_long_table(const int32_t *binlist, int64_t off, int64_t nlong, const int64_t *u,
+                       int64_t ncols, LongParams lp, LongRow *lrows, LongItem *items,
+                       LongState *state, Seq *partials, int32_t *piece_lrow, int64_t *tmp,
+                       hipStream_t s) {
+  if (nlong <= 0) return;
+  const int64_t nb = (nlong + 255) / 256;
+  hipLaunchKernelGGL(k_lt_reduce, dim3(nb), dim3(256), 0, s, binlist, off, nlong, u, ncols, lp,
+                     tmp);
+  hipLaunchKernelGGL(k_lt_scan, dim3(1), dim3(64), 0, s, tmp, nb);
+  hipLaunchKernelGGL(k_lt_write, dim3(nb), dim3(256), 0, s, binlist, off, nlong, u, ncols, lp,
+                     tmp, lrows, items, state, partials, piece_lrow);
+}
+
+// Checkpoints of the combine pieces: start of the stream, empty G.
+__global__ void k_cstate_init(LongState *state, int64_t n) {
   const int64_t x = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (x >= n) return;
   LongState s;
-  s.pos = items[x].p0;
+  s.pos = 0;
   s.gcnt = 0;
   s.gcap = 0;
   s.gcol = nullptr;
@@ -502,57 +1316,109 @@ __global__ void k_long_init(const LongItem *items, LongState *state, int64_t n) 
   state[x] = s;
 }
 
+void launch_cstate_init(LongState *state, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_cstate_init, dim3((n + 255) / 256), dim3(256), 0, s, state, n);
+}
+
+// rownnz of long rows = sum of their pieces (from the exclusive piece scan)
+__global__ void k_long_rownnz(const LongRow *lrows, int64_t nlong, const int64_t *pscan,
+                              int64_t *rownnz) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nlong) return;
+  const LongRow lr = lrows[t];
+  rownnz[lr.row] = pscan[lr.piece0 + lr.npiece] - pscan[lr.piece0];
+}
+
+void launch_long_rownnz(const LongRow *lrows, int64_t nlong, const int64_t *pscan,
+                        int64_t *rownnz, hipStream_t s) {
+  if (nlong <= 0) return;
+  hipLaunchKernelGGL(k_long_rownnz, dim3((nlong + 255) / 256), dim3(256), 0, s, lrows, nlong,
+                     pscan, rownnz);
+}
+
+// ------------------------------------------------------------ launchers
+
 int long_l1cap_default(int dtype_bytes) { return dtype_bytes == 8 ? 5120 : 7168; }
 
+constexpr int LONG_NT = 256;
+constexpr int LONG_TILE = kLongTile;
+constexpr int COMBINE_L1 = 3072;
+constexpr int COMBINE_MAXS = 512;
+
+constexpr int ONESHOT_NT = 512;
+constexpr int GENERAL_GRID = 512;  // grid of the general kernels without a work list
+
 template <typename T, int L1CAP>
-static void launch_cfg(const LongArgs<T> &a, int64_t nwork, int64_t ncols, hipStream_t s) {
-  constexpr int NT = 256, TILE = 1024;
-  if ((static_cast<uint64_t>(ncols) << Log2<TILE>::v) <= 0xffffffffull)
-    hipLaunchKernelGGL((k_long<T, NT, TILE, L1CAP, uint32_t>), dim3(nwork), dim3(NT), 0, s, a);
+static void launch_cfg(const LongArgs<T> &a, int64_t nwork, hipStream_t s) {
+  const int64_t grid = a.work ? nwork : GENERAL_GRID;
+  if ((static_cast<uint64_t>(a.ncols) << Log2<LONG_TILE>::v) <= 0xffffffffull)
+    hipLaunchKernelGGL((k_long<T, LONG_NT, LONG_TILE, L1CAP, uint32_t>), dim3(grid),
+                       dim3(LONG_NT), 0, s, a);
   else
-    hipLaunchKernelGGL((k_long<T, NT, TILE, L1CAP, uint64_t>), dim3(nwork), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_long<T, LONG_NT, LONG_TILE, L1CAP, uint64_t>), dim3(grid),
+                       dim3(LONG_NT), 0, s, a);
+}
+
+template <typename T> void launch_long_oneshot(const LongArgs<T> &a, int64_t nitems, hipStream_t s) {
+  if (nitems <= 0) return;
+  if ((static_cast<uint64_t>(a.ncols) << Log2<kOneShot>::v) <= 0xffffffffull)
+    hipLaunchKernelGGL((k_long1<T, ONESHOT_NT, kOneShot, uint32_t>), dim3(nitems),
+                       dim3(ONESHOT_NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_long1<T, ONESHOT_NT, kOneShot, uint64_t>), dim3(nitems),
+                       dim3(ONESHOT_NT), 0, s, a);
 }
 
 template <typename T>
-int launch_long(const LongArgs<T> &a, int64_t nwork, int64_t ncols, int l1cap, hipStream_t s) {
-  if (nwork <= 0) return 0;
+void launch_combine_oneshot(const LongArgs<T> &a, int64_t npieces, hipStream_t s) {
+  if (npieces <= 0) return;
+  if ((static_cast<uint64_t>(a.ncols) << Log2<kOneShot>::v) <= 0xffffffffull)
+    hipLaunchKernelGGL((k_combine1<T, ONESHOT_NT, kOneShot, uint32_t, COMBINE_MAXS>),
+                       dim3(npieces), dim3(ONESHOT_NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_combine1<T, ONESHOT_NT, kOneShot, uint64_t, COMBINE_MAXS>),
+                       dim3(npieces), dim3(ONESHOT_NT), 0, s, a);
+}
+
+template <typename T>
+int launch_long(const LongArgs<T> &a, int64_t nwork, int l1cap, hipStream_t s) {
+  if (a.work && nwork <= 0) return 0;
   switch (l1cap) {
-    case 2048: launch_cfg<T, 2048>(a, nwork, ncols, s); break;
-    case 3072: launch_cfg<T, 3072>(a, nwork, ncols, s); break;
-    case 5120: launch_cfg<T, 5120>(a, nwork, ncols, s); break;
-    case 7168: launch_cfg<T, 7168>(a, nwork, ncols, s); break;
+    case 2048: launch_cfg<T, 2048>(a, nwork, s); break;
+    case 3072: launch_cfg<T, 3072>(a, nwork, s); break;
+    case 5120: launch_cfg<T, 5120>(a, nwork, s); break;
+    case 7168: launch_cfg<T, 7168>(a, nwork, s); break;
     default: return -1;
   }
   return 0;
 }
 
-void launch_long_init(const LongItem *items, LongState *state, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_long_init, dim3((n + 255) / 256), dim3(256), 0, s, items, state, n);
+template <typename T>
+int launch_combine(const LongArgs<T> &a, int64_t npieces, hipStream_t s) {
+  if (a.work && npieces <= 0) return 0;
+  const int64_t grid = a.work ? npieces : GENERAL_GRID;
+  if ((static_cast<uint64_t>(a.ncols) << Log2<LONG_TILE>::v) <= 0xffffffffull)
+    hipLaunchKernelGGL(
+        (k_combine<T, LONG_NT, LONG_TILE, COMBINE_L1, uint32_t, COMBINE_MAXS>),
+        dim3(grid), dim3(LONG_NT), 0, s, a);
+  else
+    hipLaunchKernelGGL(
+        (k_combine<T, LONG_NT, LONG_TILE, COMBINE_L1, uint64_t, COMBINE_MAXS>),
+        dim3(grid), dim3(LONG_NT), 0, s, a);
+  return 0;
 }
 
-// One work item per long row: the rows of bin 37 in the (stable) bin list.
-__global__ void k_long_items(const int32_t *binlist, int64_t off, int64_t n, const int64_t *u,
-                             LongItem *items) {
-  const int64_t x = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (x >= n) return;
-  const int32_t row = binlist[off + x];
-  LongItem it;
-  it.row = row;
-  it.part = 0;
-  it.p0 = 0;
-  it.p1 = u[row];
-  items[x] = it;
-}
+int combine_maxs() { return COMBINE_MAXS; }
+int combine_l1cap() { return COMBINE_L1; }
 
-void launch_long_items(const int32_t *binlist, int64_t off, int64_t n, const int64_t *u,
-                       LongItem *items, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_long_items, dim3((n + 255) / 256), dim3(256), 0, s, binlist, off, n, u,
-                     items);
-}
-
-template int launch_long<float>(const LongArgs<float> &, int64_t, int64_t, int, hipStream_t);
-template int launch_long<double>(const LongArgs<double> &, int64_t, int64_t, int, hipStream_t);
+template int launch_long<float>(const LongArgs<float> &, int64_t, int, hipStream_t);
+template int launch_long<double>(const LongArgs<double> &, int64_t, int, hipStream_t);
+template int launch_combine<float>(const LongArgs<float> &, int64_t, hipStream_t);
+template int launch_combine<double>(const LongArgs<double> &, int64_t, hipStream_t);
+template void launch_long_oneshot<float>(const LongArgs<float> &, int64_t, hipStream_t);
+template void launch_long_oneshot<double>(const LongArgs<double> &, int64_t, hipStream_t);
+template void launch_combine_oneshot<float>(const LongArgs<float> &, int64_t, hipStream_t);
+template void launch_combine_oneshot<double>(const LongArgs<double> &, int64_t, hipStream_t);
 
 }  // namespace spg

@@ -46,11 +46,19 @@ def check(A, B, exact=True, **opts):
           (ref.nnz, ref.flops, err, rel), flush=True)
     assert err <= TOL[np.dtype(A.val.dtype)]
     if exact:
+        # rows summed in the oracle's order: not split into segments and not
+        # spilling out of the level-1 sequence
+        l1cap = opts.get("l1_cap") or (5120 if A.val.dtype == np.float64 else 7168)
+        seg = opts.get("seg", 0)
+        segp = np.inf if seg is not None and seg < 0 else (seg or l1cap - 1024)
+        u = ref.u
+        ok_rows = (u <= segp) & (np.minimum(u, B.cols) <= l1cap - 1024)
+        mask = np.repeat(ok_rows, np.diff(ref.row_ptr))
         if A.val.dtype == np.float64:
-            assert np.array_equal(v, ref.val), "binary64 values differ from sequential sums"
+            assert np.array_equal(v[mask], ref.val[mask]), "binary64 values differ from sequential sums"
         else:
             r32 = oracle.spgemm(A.as_tuple(), B.as_tuple(), acc32=True)
-            assert np.array_equal(v, r32.val), "binary32 values differ from sequential sums"
+            assert np.array_equal(v[mask], r32.val[mask]), "binary32 values differ from sequential sums"
     return (rp, ci, v), info
 
 
@@ -139,6 +147,34 @@ def test_pool_exhaustion_relaunch():
     A, B = S.crafted_rows([20000, 9000, 3000, 700, 40000, 600], n=60000)
     (rp0, ci0, v0), i0 = check(A, B, exact=False)
     (rp1, ci1, v1), i1 = check(A, B, exact=False, pool_entries=300)
+    assert i1.realloc_rounds > 0
+    assert np.array_equal(ci0, ci1) and np.array_equal(v0, v1)
+
+
+@pytest.mark.parametrize("seg", [1024, 2048, 4096, -1])
+def test_long_row_splitting(seg):
+    """Rows cut into product segments (phase 1) and combined per column range
+    (phase 2), or never cut (seg = -1, L1 spills into growing pool blocks):
+    identical structure, values within tolerance."""
+    A, B = S.crafted_rows([20000, 9000, 70000, 513, 30000, 3000, 600], n=60000)
+    check(A, B, exact=False, seg=seg)
+    A2, _ = S.config2(n=30000, cap=5000)
+    check(A2, A2, exact=False, seg=seg)
+
+
+def test_collision_heavy_rows_split():
+    """Workload-5-like rows (u >> n): many segments whose partials overlap in
+    almost every column."""
+    A, B = S.config5(n=20000, ncols=256)
+    check(A, B, exact=False, seg=1024)
+
+
+def test_never_split_with_tiny_pool():
+    """The paper's progressive scheme alone: unsplit long rows spill L1 into
+    pool blocks that grow 2x; a tiny pool forces checkpoint + relaunch."""
+    A, B = S.crafted_rows([20000, 9000, 3000, 700, 40000, 600], n=60000)
+    (_, ci0, v0), _ = check(A, B, exact=False, seg=-1)
+    (_, ci1, v1), i1 = check(A, B, exact=False, seg=-1, pool_entries=500)
     assert i1.realloc_rounds > 0
     assert np.array_equal(ci0, ci1) and np.array_equal(v0, v1)
 
