@@ -12,3 +12,4 @@ from .lib import (  # noqa: F401
     load,
     spgemm,
 )
+from .autograd import matmul, matmul_torch  # noqa: F401

@@ -322,7 +322,9 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   p->nwaves = (m + 63) / 64;  // one histogram column per 64-row wavefront
   p->nblocks = (m + 255) / 256;
   p->l1cap = o.l1_cap ? o.l1_cap : long_l1cap_default(dtype_bytes(p->dtype));
-  p->lp.segp = o.seg < 0 ? -1 : (o.seg > 0 ? o.seg : p->l1cap - kLongTile);
+  // default segment: one tile of the one-pass kernel, and never more than
+  // the level-1 sequence can take without spilling
+  p->lp.segp = o.seg < 0 ? -1 : (o.seg > 0 ? o.seg : std::min(p->l1cap - kLongTile, kOneShot));
   p->lp.maxs = combine_maxs();
   p->lp.cb = 2048;
   p->lp.minw_shift = 4;

@@ -1,0 +1,152 @@
+// Expand-sort-compress of up to G*K products per row by an aligned group of
+// G lanes of a wavefront (K products per lane), shared by the per-bin
+// kernels and the batched persistent kernel.  See esc.hip.
+#pragma once
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace spg {
+
+constexpr int ESC_NT = 256;
+
+template <typename T, int G, int K, typename Key> struct EscShape {
+  static constexpr int U = G * K;
+  static constexpr int RPB = ESC_NT / G;  // rows per work-group pass
+  static constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
+  static constexpr size_t a_bytes = static_cast<size_t>(RPB) * U * KB;
+  static constexpr size_t lds_bytes = a_bytes + static_cast<size_t>(RPB) * U * sizeof(T);
+};
+
+// One pass of a work-group over the rows rows[base .. base + RPB) (those
+// below nrows).  LDS per row: region A holds the run starts (int32 index
+// into B's arrays, -1 = none) and later the sorted keys; region B holds a_ij
+// of each run and later the product values.  A group's lanes share one
+// wavefront, so all reads of the first use precede the writes of the second
+// in program order.  Every thread of the work-group must call it.
+template <typename T, int G, int K, typename Key>
+DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
+                   const int64_t nrows, unsigned char *lds) {
+  using Sh = EscShape<T, G, K, Key>;
+  constexpr int U = Sh::U;
+  constexpr int LOGU = Log2<U>::v;
+  constexpr int KB = Sh::KB;
+  constexpr Key KMAX = KeyMax<Key>::v;
+  const int grp = threadIdx.x / G;
+  const int pos = threadIdx.x & (G - 1);
+  int32_t *rs = reinterpret_cast<int32_t *>(lds + grp * U * KB);
+  Key *sk = reinterpret_cast<Key *>(lds + grp * U * KB);
+  T *ra = reinterpret_cast<T *>(lds + Sh::a_bytes) + grp * U;
+  T *pv = ra;
+  // element l of a row lives at (l mod K) * G + l / K: the K elements of a
+  // lane are G apart, so lanes touch consecutive words (no bank conflicts)
+  constexpr int LOGK = Log2<K>::v;
+  auto ix = [](int l) { return (l & (K - 1)) * G + (l >> LOGK); };
+  const int64_t r = base + grp;
+  const int32_t i = r < nrows ? rows[r] : 0;
+  // rows of this launch have u <= U by binning; the check keeps every LDS
+  // and global index in range even if that were violated
+  const bool act = r < nrows && a.u[i] <= U;
+  const int u = act ? static_cast<int>(a.u[i]) : 0;
+  const int32_t e0 = act ? a.arp[i] : 0;
+  const int32_t e1 = act ? a.arp[i + 1] : 0;
+  const int64_t pbase = act ? a.P[e0] : 0;
+
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) rs[kk * G + pos] = -1;
+  __syncthreads();
+  // run starts: entry e of row i contributes products [P[e]-P[e0], P[e+1]-P[e0])
+  for (int32_t e = e0 + pos; e < e1; e += G) {
+    const int64_t s0 = a.P[e] - pbase;
+    const int64_t w = a.P[e + 1] - a.P[e];
+    if (w > 0) {
+      const int32_t j = a.acol[e];
+      rs[ix(static_cast<int>(s0))] = a.brp[j];
+      ra[ix(static_cast<int>(s0))] = a.aval[e];
+    }
+  }
+  __syncthreads();
+
+  // segmented max-scan: the run containing product l starts at s(l)
+  int st[K];
+  int run = -1;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    const int f = (l < u && rs[ix(l)] >= 0) ? l : -1;
+    run = max(run, f);
+    st[kk] = run;
+  }
+  const int incl = group_incl_max<G>(run);
+  int prev = __shfl_up(incl, 1, WAVE);
+  if (pos == 0) prev = -1;
+
+  Key key[K];
+  T prod[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    key[kk] = KMAX;
+    prod[kk] = T(0);
+    const int s0 = max(prev, st[kk]);
+    if (l < u && s0 >= 0) {
+      const int32_t bidx = rs[ix(s0)] + (l - s0);
+      const T av = ra[ix(s0)];
+      const int32_t c = a.bcol[bidx];
+      const T bv = a.bval[bidx];
+      prod[kk] = av * bv;
+      key[kk] = (static_cast<Key>(c) << LOGU) | static_cast<Key>(l);
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    if (l < u) pv[ix(l)] = prod[kk];
+  }
+
+  group_bitonic_sort<G, K, Key>(key);
+
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) sk[kk * G + pos] = key[kk];
+  const Key pk = shfl_up_key<Key>(key[K - 1], 1);
+  __syncthreads();
+
+  // compress: count the distinct columns, place them with a group scan,
+  // then fold every column's products in expansion order
+  uint32_t hmask = 0;
+  int nh = 0;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    const Key before = kk > 0 ? key[kk - 1] : pk;
+    const bool head = l < u && (l == 0 || (before >> LOGU) != (key[kk] >> LOGU));
+    hmask |= head ? (1u << kk) : 0u;
+    nh += head ? 1 : 0;
+  }
+  const int incl_h = group_incl_sum<G>(nh);
+  const int total = group_last<G>(incl_h);
+  if (act) {
+    int64_t o = a.cto[i] + (incl_h - nh);
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      if (hmask & (1u << kk)) {
+        const int l = pos * K + kk;
+        const Key c = key[kk] >> LOGU;
+        T v = T(0);
+        v = v + pv[ix(static_cast<int>(key[kk] & (U - 1)))];
+        for (int l2 = l + 1; l2 < u; ++l2) {
+          const Key k2 = sk[ix(l2)];
+          if ((k2 >> LOGU) != c) break;
+          v = v + pv[ix(static_cast<int>(k2 & (U - 1)))];
+        }
+        a.ct_col[o] = static_cast<int32_t>(c);
+        a.ct_val[o] = v;
+        ++o;
+      }
+    }
+    if (pos == 0) a.rownnz[i] = total;
+  }
+  __syncthreads();
+}
+
+}  // namespace spg

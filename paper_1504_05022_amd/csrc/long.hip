@@ -153,6 +153,11 @@ DEVI bool pool_alloc(Pool *pool, uint64_t cap, int32_t *&col, T *&val) {
   return true;
 }
 
+// Tile element l lives at (l mod KT) * NT + l / KT: the KT elements of a
+// thread are NT apart, so the threads of a wavefront touch consecutive words
+// (no LDS bank conflicts on the regular accesses).
+template <int NT, int KT> DEVI int tix(int l) { return (l & (KT - 1)) * NT + (l >> Log2<KT>::v); }
+
 // Sort a tile (keys col << LOGT | position, values pv[position] in LDS),
 // fold every column into L1 (binary-search fuse; new columns are compacted
 // with a prefix sum) and merge the new columns into L1 with merge path.
@@ -168,7 +173,7 @@ DEVI void tile_insert(Key (&key)[TILE / NT], const int tn, Key *sk, T *pv, int32
   const int t = threadIdx.x;
   block_bitonic_sort<NT, KT, Key>(key, sk);
 #pragma unroll
-  for (int kk = 0; kk < KT; ++kk) sk[t * KT + kk] = key[kk];
+  for (int kk = 0; kk < KT; ++kk) sk[kk * NT + t] = key[kk];
   __syncthreads();
 
   bool isnew[KT];
@@ -183,7 +188,7 @@ DEVI void tile_insert(Key (&key)[TILE / NT], const int tn, Key *sk, T *pv, int32
     nv[kk] = T(0);
     if (l < tn) {
       const Key c = key[kk] >> LOGT;
-      const bool head = (l == 0) || ((sk[l - 1] >> LOGT) != c);
+      const bool head = (l == 0) || ((sk[tix<NT, KT>(l - 1)] >> LOGT) != c);
       if (head) {
         const int32_t col = col_base + static_cast<int32_t>(c);
         int lo = 0, hi = r;
@@ -196,11 +201,11 @@ DEVI void tile_insert(Key (&key)[TILE / NT], const int tn, Key *sk, T *pv, int32
         }
         const bool found = lo < r && l1c[lo] == col;
         T v = found ? l1v[lo] : T(0);
-        v = v + pv[static_cast<int>(key[kk] & (TILE - 1))];
+        v = v + pv[tix<NT, KT>(static_cast<int>(key[kk] & (TILE - 1)))];
         for (int l2 = l + 1; l2 < tn; ++l2) {
-          const Key k2 = sk[l2];
+          const Key k2 = sk[tix<NT, KT>(l2)];
           if ((k2 >> LOGT) != c) break;
-          v = v + pv[static_cast<int>(k2 & (TILE - 1))];
+          v = v + pv[tix<NT, KT>(static_cast<int>(k2 & (TILE - 1)))];
         }
         if (found) {
           l1v[lo] = v;
@@ -434,7 +439,7 @@ DEVI void long_item(LongArgs<T> &a, const int32_t item_id) {
 
     // run starts of the entries overlapping [pos, pos+tn)
 #pragma unroll
-    for (int kk = 0; kk < KT; ++kk) rs[t * KT + kk] = -1;
+    for (int kk = 0; kk < KT; ++kk) rs[kk * NT + t] = -1;
     if (t == 0) sh.next_first = e_first;
     __syncthreads();
     for (int32_t e = e_first + t; e < e1; e += NT) {
@@ -450,8 +455,8 @@ DEVI void long_item(LongArgs<T> &a, const int32_t item_id) {
           off = static_cast<int32_t>(-ls);
           ls = 0;
         }
-        rs[ls] = a.e.brp[j] + off;
-        ra[ls] = a.e.aval[e];
+        rs[tix<NT, KT>(static_cast<int>(ls))] = a.e.brp[j] + off;
+        ra[tix<NT, KT>(static_cast<int>(ls))] = a.e.aval[e];
       }
     }
     __syncthreads();
@@ -462,7 +467,7 @@ DEVI void long_item(LongArgs<T> &a, const int32_t item_id) {
 #pragma unroll
     for (int kk = 0; kk < KT; ++kk) {
       const int l = t * KT + kk;
-      const int f = (l < tn && rs[l] >= 0) ? l : -1;
+      const int f = (l < tn && rs[tix<NT, KT>(l)] >= 0) ? l : -1;
       run = max(run, f);
       st_run[kk] = run;
     }
@@ -476,8 +481,8 @@ DEVI void long_item(LongArgs<T> &a, const int32_t item_id) {
       prod[kk] = T(0);
       const int s0 = max(before, st_run[kk]);
       if (l < tn && s0 >= 0) {
-        const int32_t bidx = rs[s0] + (l - s0);
-        const T av = ra[s0];
+        const int32_t bidx = rs[tix<NT, KT>(s0)] + (l - s0);
+        const T av = ra[tix<NT, KT>(s0)];
         const int32_t c = a.e.bcol[bidx];
         const T bv = a.e.bval[bidx];
         prod[kk] = av * bv;
@@ -488,7 +493,7 @@ DEVI void long_item(LongArgs<T> &a, const int32_t item_id) {
 #pragma unroll
     for (int kk = 0; kk < KT; ++kk) {
       const int l = t * KT + kk;
-      if (l < tn) pv[l] = prod[kk];
+      if (l < tn) pv[tix<NT, KT>(l)] = prod[kk];
     }
     tile_insert<T, NT, TILE, L1CAP, Key>(key, tn, sk, pv, ncol, nval, l1c, l1v, r, 0, sh.scan);
     pos += tn;
@@ -699,7 +704,7 @@ DEVI void combine_piece(LongArgs<T> &a, const int32_t pid) {
 #pragma unroll
     for (int kk = 0; kk < KT; ++kk) {
       const int l = t * KT + kk;
-      if (l < tn) pv[l] = val[kk];
+      if (l < tn) pv[tix<NT, KT>(l)] = val[kk];
     }
     tile_insert<T, NT, TILE, L1CAP, Key>(key, tn, sk, pv, ncol, nval, l1c, l1v, r, c0, sh.scan);
     pos += tn;
@@ -803,7 +808,7 @@ __global__ __launch_bounds__(NT) void k_combine(LongArgs<T> a) {
 
 // Output of a one-tile pass: head flags and the running output index.
 // Writes the range starts of a multi-segment row's partial from the heads.
-template <typename Key, int KT, int LOGT>
+template <typename Key, int NT, int KT, int LOGT>
 DEVI void oneshot_split_points(const Key (&key)[KT], const bool (&hd)[KT], const int32_t (&ho)[KT],
                                const Key *sk, int tn, int r, int32_t col_base, int shift,
                                int32_t np, int32_t *pos, int32_t nseg, int32_t s) {
@@ -815,7 +820,7 @@ DEVI void oneshot_split_points(const Key (&key)[KT], const bool (&hd)[KT], const
       const int32_t c = col_base + static_cast<int32_t>(key[kk] >> LOGT);
       const int32_t b = c >> shift;
       const int32_t bp =
-          l > 0 ? ((col_base + static_cast<int32_t>(sk[l - 1] >> LOGT)) >> shift) : -1;
+          l > 0 ? ((col_base + static_cast<int32_t>(sk[tix<NT, KT>(l - 1)] >> LOGT)) >> shift) : -1;
       for (int32_t q = bp + 1; q <= b && q < np; ++q)
         pos[static_cast<int64_t>(q) * nseg + s] = ho[kk];
     }
@@ -827,28 +832,18 @@ DEVI void oneshot_split_points(const Key (&key)[KT], const bool (&hd)[KT], const
   }
 }
 
-template <typename T, int NT, int TILE, typename Key>
-__global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
-  constexpr int KT = TILE / NT;
+template <typename T, int NT, int KT, typename Key>
+DEVI void long1_body(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
+                     unsigned char *s_a, T *s_b, MergeShared<T> &sh) {
+  constexpr int TILE = NT * KT;
   constexpr int LOGT = Log2<TILE>::v;
   constexpr Key KMAX = KeyMax<Key>::v;
-  constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
-  __shared__ __align__(16) unsigned char s_a[TILE * KB];  // run starts / keys
-  __shared__ __align__(16) T s_b[TILE];                    // a_ij of runs / products
-  __shared__ MergeShared<T> sh;
   int32_t *rs = reinterpret_cast<int32_t *>(s_a);
   Key *sk = reinterpret_cast<Key *>(s_a);
   T *ra = s_b;
   T *pv = s_b;
-
   const int t = threadIdx.x;
-  const int32_t item_id = static_cast<int32_t>(blockIdx.x);
-  const LongItem item = a.items[item_id];
   const int64_t p0 = item.p0, p1 = item.p1;
-  if (p1 - p0 > TILE) {
-    if (t == 0) a.glist[atomicAdd(&a.cnt->glong, 1u)] = static_cast<unsigned int>(item_id);
-    return;
-  }
   const LongRow lr = a.lrows[item.lrow];
   const int32_t i = item.row;
   const int32_t e1 = a.e.arp[i + 1];
@@ -856,7 +851,7 @@ __global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
   const int tn = static_cast<int>(p1 - p0);
 
 #pragma unroll
-  for (int kk = 0; kk < KT; ++kk) rs[t * KT + kk] = -1;
+  for (int kk = 0; kk < KT; ++kk) rs[kk * NT + t] = -1;
   __syncthreads();
   for (int32_t e = item.e_first + t; e < e1; e += NT) {
     const int64_t s0 = a.e.P[e] - pbase;
@@ -869,8 +864,8 @@ __global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
         off = static_cast<int32_t>(-ls);
         ls = 0;
       }
-      rs[ls] = a.e.brp[a.e.acol[e]] + off;
-      ra[ls] = a.e.aval[e];
+      rs[tix<NT, KT>(static_cast<int>(ls))] = a.e.brp[a.e.acol[e]] + off;
+      ra[tix<NT, KT>(static_cast<int>(ls))] = a.e.aval[e];
     }
   }
   __syncthreads();
@@ -879,7 +874,7 @@ __global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
 #pragma unroll
   for (int kk = 0; kk < KT; ++kk) {
     const int l = t * KT + kk;
-    const int f = (l < tn && rs[l] >= 0) ? l : -1;
+    const int f = (l < tn && rs[tix<NT, KT>(l)] >= 0) ? l : -1;
     run = max(run, f);
     st_run[kk] = run;
   }
@@ -893,8 +888,8 @@ __global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
     prod[kk] = T(0);
     const int s0 = max(before, st_run[kk]);
     if (l < tn && s0 >= 0) {
-      const int32_t bidx = rs[s0] + (l - s0);
-      const T av = ra[s0];
+      const int32_t bidx = rs[tix<NT, KT>(s0)] + (l - s0);
+      const T av = ra[tix<NT, KT>(s0)];
       const int32_t c = a.e.bcol[bidx];
       prod[kk] = av * a.e.bval[bidx];
       key[kk] = (static_cast<Key>(c) << LOGT) | static_cast<Key>(l);
@@ -904,11 +899,11 @@ __global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
 #pragma unroll
   for (int kk = 0; kk < KT; ++kk) {
     const int l = t * KT + kk;
-    if (l < tn) pv[l] = prod[kk];
+    if (l < tn) pv[tix<NT, KT>(l)] = prod[kk];
   }
   block_bitonic_sort<NT, KT, Key>(key, sk);
 #pragma unroll
-  for (int kk = 0; kk < KT; ++kk) sk[t * KT + kk] = key[kk];
+  for (int kk = 0; kk < KT; ++kk) sk[kk * NT + t] = key[kk];
   __syncthreads();
 
   bool hd[KT];
@@ -916,7 +911,7 @@ __global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
 #pragma unroll
   for (int kk = 0; kk < KT; ++kk) {
     const int l = t * KT + kk;
-    hd[kk] = l < tn && (l == 0 || (sk[l - 1] >> LOGT) != (key[kk] >> LOGT));
+    hd[kk] = l < tn && (l == 0 || (sk[tix<NT, KT>(l - 1)] >> LOGT) != (key[kk] >> LOGT));
     nh += hd[kk] ? 1 : 0;
   }
   int64_t rtot;
@@ -960,11 +955,11 @@ __global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
     if (hd[kk]) {
       const Key c = key[kk] >> LOGT;
       T v = T(0);
-      v = v + pv[static_cast<int>(key[kk] & (TILE - 1))];
+      v = v + pv[tix<NT, KT>(static_cast<int>(key[kk] & (TILE - 1)))];
       for (int l2 = l + 1; l2 < tn; ++l2) {
-        const Key k2 = sk[l2];
+        const Key k2 = sk[tix<NT, KT>(l2)];
         if ((k2 >> LOGT) != c) break;
-        v = v + pv[static_cast<int>(k2 & (TILE - 1))];
+        v = v + pv[tix<NT, KT>(static_cast<int>(k2 & (TILE - 1)))];
       }
       dcol[o] = static_cast<int32_t>(c);
       dval[o] = v;
@@ -972,7 +967,7 @@ __global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
     }
   }
   if (!single)
-    oneshot_split_points<Key, KT, LOGT>(key, hd, ho, sk, tn, r, 0, lr.shift, lr.npiece,
+    oneshot_split_points<Key, NT, KT, LOGT>(key, hd, ho, sk, tn, r, 0, lr.shift, lr.npiece,
                                         a.split + lr.sbase, lr.nseg,
                                         static_cast<int32_t>(item_id - lr.item0));
   if (t == 0) {
@@ -998,11 +993,147 @@ __global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
   }
 }
 
+
+template <typename T, int NT, int TILE, typename Key>
+__global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
+  constexpr int KT = TILE / NT;
+  constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
+  __shared__ __align__(16) unsigned char s_a[TILE * KB];  // run starts / keys
+  __shared__ __align__(16) T s_b[TILE];                    // a_ij of runs / products
+  __shared__ MergeShared<T> sh;
+  const int32_t item_id = static_cast<int32_t>(blockIdx.x);
+  const LongItem item = a.items[item_id];
+  const int64_t size = item.p1 - item.p0;
+  if (size > TILE) {
+    if (threadIdx.x == 0)
+      a.glist[atomicAdd(&a.cnt->glong, 1u)] = static_cast<unsigned int>(item_id);
+    return;
+  }
+  // the sorting network only as large as the item needs
+  if (size <= TILE / 4)
+    long1_body<T, NT, KT / 4, Key>(a, item_id, item, s_a, s_b, sh);
+  else if (size <= TILE / 2)
+    long1_body<T, NT, KT / 2, Key>(a, item_id, item, s_a, s_b, sh);
+  else
+    long1_body<T, NT, KT, Key>(a, item_id, item, s_a, s_b, sh);
+}
+
+template <typename T, int NT, int KT, typename Key, int MAXS>
+DEVI void combine1_body(LongArgs<T> &a, const int32_t pid, const int32_t lri, const int32_t c0,
+                        const int32_t nseg, const int64_t E, const int32_t *sg_off,
+                        const int32_t *sg_lo, const int32_t *const *sg_col,
+                        const T *const *sg_val, unsigned char *s_a, T *s_b,
+                        MergeShared<T> &sh) {
+  constexpr int TILE = NT * KT;
+  constexpr int LOGT = Log2<TILE>::v;
+  constexpr Key KMAX = KeyMax<Key>::v;
+  Key *sk = reinterpret_cast<Key *>(s_a);
+  T *pv = s_b;
+  const int t = threadIdx.x;
+  const int tn = static_cast<int>(E);
+  Key key[KT];
+  T val[KT];
+  {
+    const int g0 = t * KT;
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (sg_off[mid] <= g0)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    int s = lo;
+#pragma unroll
+    for (int kk = 0; kk < KT; ++kk) {
+      const int l = t * KT + kk;
+      key[kk] = KMAX;
+      val[kk] = T(0);
+      if (l < tn) {
+        while (s + 1 < nseg && sg_off[s + 1] <= l) ++s;
+        const int64_t idx = sg_lo[s] + (l - sg_off[s]);
+        const int32_t c = sg_col[s][idx];
+        val[kk] = sg_val[s][idx];
+        key[kk] = (static_cast<Key>(c - c0) << LOGT) | static_cast<Key>(l);
+      }
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    if (l < tn) pv[tix<NT, KT>(l)] = val[kk];
+  }
+  block_bitonic_sort<NT, KT, Key>(key, sk);
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) sk[kk * NT + t] = key[kk];
+  __syncthreads();
+  bool hd[KT];
+  int nh = 0;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    hd[kk] = l < tn && (l == 0 || (sk[tix<NT, KT>(l - 1)] >> LOGT) != (key[kk] >> LOGT));
+    nh += hd[kk] ? 1 : 0;
+  }
+  int64_t rtot;
+  int o = static_cast<int>(block_excl_sum<NT>(static_cast<int64_t>(nh), sh.scan, rtot));
+  const int r = static_cast<int>(rtot);
+  if (t == 0) {
+    sh.ok = 1;
+    int32_t *zc = nullptr;
+    T *zv = nullptr;
+    if (r == 0) {
+      sh.zcol = nullptr;
+      sh.zval = nullptr;
+    } else if (pool_alloc<T>(a.pool, static_cast<uint64_t>(r), zc, zv)) {
+      sh.zcol = zc;
+      sh.zval = zv;
+    } else {
+      sh.ok = 0;
+    }
+  }
+  __syncthreads();
+  if (!sh.ok) {
+    if (t == 0) a.glist2[atomicAdd(&a.cnt->gcomb, 1u)] = static_cast<unsigned int>(pid);
+    return;
+  }
+  int32_t *dcol = sh.zcol;
+  T *dval = sh.zval;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    if (hd[kk]) {
+      const Key c = key[kk] >> LOGT;
+      T v = T(0);
+      v = v + pv[tix<NT, KT>(static_cast<int>(key[kk] & (TILE - 1)))];
+      for (int l2 = l + 1; l2 < tn; ++l2) {
+        const Key k2 = sk[tix<NT, KT>(l2)];
+        if ((k2 >> LOGT) != c) break;
+        v = v + pv[tix<NT, KT>(static_cast<int>(k2 & (TILE - 1)))];
+      }
+      dcol[o] = c0 + static_cast<int32_t>(c);
+      dval[o] = v;
+      ++o;
+    }
+  }
+  if (t == 0) {
+    LongState st = a.cstate[pid];
+    st.pos = E;
+    a.cstate[pid] = st;
+    Piece pc;
+    pc.col = dcol;
+    pc.val = dval;
+    pc.cnt = r;
+    pc.lrow = lri;
+    pc.pad = 0;
+    a.pieces[pid] = pc;
+  }
+}
+
+
 template <typename T, int NT, int TILE, typename Key, int MAXS>
 __global__ __launch_bounds__(NT) void k_combine1(LongArgs<T> a) {
   constexpr int KT = TILE / NT;
-  constexpr int LOGT = Log2<TILE>::v;
-  constexpr Key KMAX = KeyMax<Key>::v;
   constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
   __shared__ __align__(16) unsigned char s_a[TILE * KB];
   __shared__ __align__(16) T s_b[TILE];
@@ -1011,9 +1142,6 @@ __global__ __launch_bounds__(NT) void k_combine1(LongArgs<T> a) {
   __shared__ const int32_t *sg_col[MAXS];
   __shared__ const T *sg_val[MAXS];
   __shared__ MergeShared<T> sh;
-  Key *sk = reinterpret_cast<Key *>(s_a);
-  T *pv = s_b;
-
   const int t = threadIdx.x;
   const int32_t pid = static_cast<int32_t>(blockIdx.x);
   const int32_t lri = a.piece_lrow[pid];
@@ -1053,104 +1181,15 @@ __global__ __launch_bounds__(NT) void k_combine1(LongArgs<T> a) {
     if (t == 0) a.glist2[atomicAdd(&a.cnt->gcomb, 1u)] = static_cast<unsigned int>(pid);
     return;
   }
-  const int tn = static_cast<int>(E);
-  Key key[KT];
-  T val[KT];
-  {
-    const int g0 = t * KT;
-    int lo = 0, hi = nseg;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (sg_off[mid] <= g0)
-        lo = mid;
-      else
-        hi = mid;
-    }
-    int s = lo;
-#pragma unroll
-    for (int kk = 0; kk < KT; ++kk) {
-      const int l = t * KT + kk;
-      key[kk] = KMAX;
-      val[kk] = T(0);
-      if (l < tn) {
-        while (s + 1 < nseg && sg_off[s + 1] <= l) ++s;
-        const int64_t idx = sg_lo[s] + (l - sg_off[s]);
-        const int32_t c = sg_col[s][idx];
-        val[kk] = sg_val[s][idx];
-        key[kk] = (static_cast<Key>(c - c0) << LOGT) | static_cast<Key>(l);
-      }
-    }
-  }
-#pragma unroll
-  for (int kk = 0; kk < KT; ++kk) {
-    const int l = t * KT + kk;
-    if (l < tn) pv[l] = val[kk];
-  }
-  block_bitonic_sort<NT, KT, Key>(key, sk);
-#pragma unroll
-  for (int kk = 0; kk < KT; ++kk) sk[t * KT + kk] = key[kk];
-  __syncthreads();
-  bool hd[KT];
-  int nh = 0;
-#pragma unroll
-  for (int kk = 0; kk < KT; ++kk) {
-    const int l = t * KT + kk;
-    hd[kk] = l < tn && (l == 0 || (sk[l - 1] >> LOGT) != (key[kk] >> LOGT));
-    nh += hd[kk] ? 1 : 0;
-  }
-  int64_t rtot;
-  int o = static_cast<int>(block_excl_sum<NT>(static_cast<int64_t>(nh), sh.scan, rtot));
-  const int r = static_cast<int>(rtot);
-  if (t == 0) {
-    sh.ok = 1;
-    int32_t *zc = nullptr;
-    T *zv = nullptr;
-    if (r == 0) {
-      sh.zcol = nullptr;
-      sh.zval = nullptr;
-    } else if (pool_alloc<T>(a.pool, static_cast<uint64_t>(r), zc, zv)) {
-      sh.zcol = zc;
-      sh.zval = zv;
-    } else {
-      sh.ok = 0;
-    }
-  }
-  __syncthreads();
-  if (!sh.ok) {
-    if (t == 0) a.glist2[atomicAdd(&a.cnt->gcomb, 1u)] = static_cast<unsigned int>(pid);
-    return;
-  }
-  int32_t *dcol = sh.zcol;
-  T *dval = sh.zval;
-#pragma unroll
-  for (int kk = 0; kk < KT; ++kk) {
-    const int l = t * KT + kk;
-    if (hd[kk]) {
-      const Key c = key[kk] >> LOGT;
-      T v = T(0);
-      v = v + pv[static_cast<int>(key[kk] & (TILE - 1))];
-      for (int l2 = l + 1; l2 < tn; ++l2) {
-        const Key k2 = sk[l2];
-        if ((k2 >> LOGT) != c) break;
-        v = v + pv[static_cast<int>(k2 & (TILE - 1))];
-      }
-      dcol[o] = c0 + static_cast<int32_t>(c);
-      dval[o] = v;
-      ++o;
-    }
-  }
-  if (t == 0) {
-    LongState st = a.cstate[pid];
-    st.pos = E;
-    a.cstate[pid] = st;
-    Piece pc;
-    pc.col = dcol;
-    pc.val = dval;
-    pc.cnt = r;
-    pc.lrow = lri;
-    pc.pad = 0;
-    a.pieces[pid] = pc;
-  }
+  if (E <= TILE / 4)
+    combine1_body<T, NT, KT / 4, Key, MAXS>(a, pid, lri, c0, nseg, E, sg_off, sg_lo, sg_col,
+                                            sg_val, s_a, s_b, sh);
+  else if (E <= TILE / 2)
+    combine1_body<T, NT, KT / 2, Key, MAXS>(a, pid, lri, c0, nseg, E, sg_off, sg_lo, sg_col,
+                                            sg_val, s_a, s_b, sh);
+  else
+    combine1_body<T, NT, KT, Key, MAXS>(a, pid, lri, c0, nseg, E, sg_off, sg_lo, sg_col,
+                                        sg_val, s_a, s_b, sh);
 }
 
 // Entry of A's row that contains the first product of every item.

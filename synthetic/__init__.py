@@ -21,6 +21,7 @@ from .gen import (  # noqa: F401
     config2,
     config3,
     config4,
+    config4_sizes,
     config5,
     config5_dc,
     crafted_rows,

@@ -274,12 +274,19 @@ def config3(g=64):
     return stencil27(g), aggregation_p(g), aggregation_r(g)
 
 
-def config4(count=512, nmin=1024, nmax=65536, dmin=4, dmax=32, band=0.05):
-    """Workload 4: list of (A_i, B_i); binary64 for even i, binary32 for odd i."""
+def config4_sizes(count=512, nmin=1024, nmax=65536):
+    """Matrix sizes of workload 4 (log-uniform in [nmin, nmax])."""
     sizes = rng_for(4, 0)
-    ns = np.exp(sizes.uniform(math.log(nmin), math.log(nmax), count)).round().astype(np.int64)
+    return np.exp(sizes.uniform(math.log(nmin), math.log(nmax), count)).round().astype(np.int64)
+
+
+def config4(count=512, nmin=1024, nmax=65536, dmin=4, dmax=32, band=0.05, only=None):
+    """Workload 4: list of (A_i, B_i); binary64 for even i, binary32 for odd i.
+    ``only``: generate just these problem indices (same matrices as in the
+    full batch)."""
+    ns = config4_sizes(count, nmin, nmax)
     out = []
-    for p in range(count):
+    for p in (range(count) if only is None else only):
         dt = np.float64 if p % 2 == 0 else np.float32
         rng = rng_for(4, 1, p)
         A = banded_csr(int(ns[p]), dmin, dmax, band, rng, dt)
