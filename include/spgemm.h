@@ -89,7 +89,7 @@ typedef struct {
   /* upper row sizes of: the single-size bins (group 3, default 32), then the
    * four range bins of group 4 (defaults 64, 128, 256, 512).  Rows above the
    * last edge form bin 37 (group 5).  Strictly increasing, edge[0] in
-   * [1, 32], edge[4] <= 2048. */
+   * [1, 32], edge[4] <= 1024. */
   int32_t bin_edges[5];
   int32_t long_slot;    /* C~ entries reserved per long row (default 256)     */
   int32_t l1_cap;       /* level-1 (LDS) sequence entries of the long-row
@@ -191,6 +191,50 @@ int spgemm_plan_info(spgemm_plan plan, spgemm_info *info);
 
 /* Release the plan and its scratch (ordered on the plan's last stream). */
 int spgemm_plan_destroy(spgemm_plan plan);
+
+/* ------------------------------------------------------------------------
+ * Batched products (extension beyond the paper): many independent
+ * C_p = A_p * B_p of uneven sizes and mixed binary32/binary64 values,
+ * computed by one persistent kernel launch replayed from a HIP graph.
+ */
+typedef struct spgemm_batch_s *spgemm_batch;
+
+typedef struct {
+  int32_t count;        /* problems                                           */
+  int32_t fallback;     /* problems recomputed with the plain path per run    */
+  int32_t grid;         /* work-groups of the persistent kernel               */
+  int32_t pad;
+  int64_t items;        /* work items in the queue                            */
+  int64_t flops;        /* sum of 2 * sum(u_i) over the problems              */
+  int64_t nnz_c;        /* sum of nnz(C_p)                                    */
+  int32_t bin_edges[5]; /* thresholds chosen by the autotuner                 */
+  float tune_ms[4];     /* timed candidates (ms per run)                      */
+} spgemm_batch_stats;
+
+/*
+ * Analyze `count` problems (A[p], B[p]: borrowed CSR views that must stay
+ * valid, with unchanged patterns, for the batch's lifetime; values may
+ * change between runs), compute every C_p once, allocate the outputs with
+ * alloc_fn, tune the bin thresholds (unless opt sets non-default ones) by
+ * timing the batched kernel, and capture the graph.  Rows with more than
+ * 1024 products (or n_p * 1024 >= 2^32) make their problem fall back to the
+ * plain path inside spgemm_batch_run.  Synchronizes `stream`.
+ */
+int spgemm_batch_create(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
+                        const spgemm_options *opt, spgemm_alloc_fn alloc_fn,
+                        spgemm_free_fn free_fn, void *ctx, void *stream, spgemm_batch *batch,
+                        spgemm_batch_stats *stats);
+
+/* Recompute every C_p (structure and values) by replaying the graph on
+ * `stream`; asynchronous unless problems fall back to the plain path.  If C
+ * is not NULL it receives `count` views of the outputs, which stay owned by
+ * the batch (valid until spgemm_batch_destroy). */
+int spgemm_batch_run(spgemm_batch batch, spgemm_csr_out *C, void *stream);
+
+int spgemm_batch_stats_get(spgemm_batch batch, spgemm_batch_stats *stats);
+
+/* Release the graph, the plans and the outputs. */
+int spgemm_batch_destroy(spgemm_batch batch);
 
 #ifdef __cplusplus
 }

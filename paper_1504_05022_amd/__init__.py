@@ -5,6 +5,7 @@ per-bin insert kernels, compaction) as hand-written HIP kernels for gfx950
 behind the C ABI in include/spgemm.h; this package is its Python binding.
 """
 from .lib import (  # noqa: F401
+    Batch,
     CsrMatrix,
     Plan,
     SpgemmError,

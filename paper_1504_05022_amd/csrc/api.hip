@@ -859,3 +859,12 @@ extern "C" int spgemm_backward(spgemm_plan plan, const spgemm_csr *A, const spge
   if (e != hipSuccess) return hip_fail(e, "backward");
   return SPGEMM_OK;
 }
+
+namespace spg {
+const int64_t *plan_rowoff(spgemm_plan p) { return p->rowoff; }
+const int64_t *plan_scan(spgemm_plan p) { return p->P; }
+const int64_t *plan_upper(spgemm_plan p) { return p->u; }
+int64_t *plan_rownnz(spgemm_plan p) { return p->rownnz; }
+const int32_t *plan_binlist(spgemm_plan p) { return p->binlist; }
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+}  // namespace spg

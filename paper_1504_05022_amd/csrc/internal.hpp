@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/spgemm.h"
 
 namespace spg {
@@ -336,5 +338,13 @@ void launch_zero(void *p, size_t bytes, hipStream_t s);
 void launch_set_pool(Pool *dst, Pool value, hipStream_t s);
 void launch_status(const int64_t *rowoff, int64_t m, const Pool *pool, ComputeStatus *st,
                    hipStream_t s);
+
+// Access to a plan's device arrays (defined with the plan in api.hip).
+const int64_t *plan_rowoff(spgemm_plan p);
+const int64_t *plan_scan(spgemm_plan p);
+const int64_t *plan_upper(spgemm_plan p);
+int64_t *plan_rownnz(spgemm_plan p);
+const int32_t *plan_binlist(spgemm_plan p);
+void set_last_error(const std::string &msg);
 
 }  // namespace spg

@@ -67,9 +67,23 @@ class Info(ctypes.Structure):
         return d
 
 
+class BatchStats(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("items", ctypes.c_int64), ("flops", ctypes.c_int64), ("nnz_c", ctypes.c_int64),
+                ("bin_edges", ctypes.c_int32 * 5), ("tune_ms", ctypes.c_float * 4)]
+
+    def as_dict(self):
+        return {"count": self.count, "fallback": self.fallback, "grid": self.grid,
+                "items": self.items, "flops": self.flops, "nnz_c": self.nnz_c,
+                "bin_edges": list(self.bin_edges), "tune_ms": list(self.tune_ms)}
+
+
 # exported symbols declared in include/spgemm.h
 EXPORTS = ("spgemm_default_options", "spgemm_strerror", "spgemm_last_error", "spgemm_analyze",
-           "spgemm_compute", "spgemm_backward", "spgemm_plan_info", "spgemm_plan_destroy")
+           "spgemm_compute", "spgemm_backward", "spgemm_plan_info", "spgemm_plan_destroy",
+           "spgemm_batch_create", "spgemm_batch_run", "spgemm_batch_stats_get",
+           "spgemm_batch_destroy")
 
 _ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -126,6 +140,17 @@ def load(path: str = LIB_PATH):
     lib.spgemm_plan_info.restype = ctypes.c_int
     lib.spgemm_plan_destroy.argtypes = [P]
     lib.spgemm_plan_destroy.restype = ctypes.c_int
+    lib.spgemm_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(CsrDesc),
+                                        ctypes.POINTER(CsrDesc), ctypes.POINTER(Options),
+                                        _ALLOC_T, _FREE_T, P, P, ctypes.POINTER(P),
+                                        ctypes.POINTER(BatchStats)]
+    lib.spgemm_batch_create.restype = ctypes.c_int
+    lib.spgemm_batch_run.argtypes = [P, ctypes.POINTER(CsrOut), P]
+    lib.spgemm_batch_run.restype = ctypes.c_int
+    lib.spgemm_batch_stats_get.argtypes = [P, ctypes.POINTER(BatchStats)]
+    lib.spgemm_batch_stats_get.restype = ctypes.c_int
+    lib.spgemm_batch_destroy.argtypes = [P]
+    lib.spgemm_batch_destroy.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -283,3 +308,58 @@ def spgemm(A: CsrMatrix, B: CsrMatrix, return_info=False, **kw):
     finally:
         plan.close()
     return (C, info) if return_info else C
+
+
+def _view(ptr, nbytes, dtype):
+    """A tensor view of library-owned memory that came from the allocator."""
+    return _live[ptr][:nbytes].view(dtype)
+
+
+class Batch:
+    """Many independent products C_p = A_p * B_p in one graph-replayed launch.
+
+    ``pairs``: list of (A_p, B_p) CsrMatrix pairs (binary32 and binary64 may
+    be mixed).  The matrices must stay alive and keep their patterns.
+    """
+
+    def __init__(self, pairs, options: Options | None = None, **kw):
+        lib = load()
+        self.pairs = list(pairs)
+        n = len(self.pairs)
+        self._A = (CsrDesc * max(n, 1))(*[a.desc() for a, _ in self.pairs])
+        self._B = (CsrDesc * max(n, 1))(*[b.desc() for _, b in self.pairs])
+        opts = options if options is not None else default_options(**kw)
+        self._h = ctypes.c_void_p()
+        st = BatchStats()
+        rc = lib.spgemm_batch_create(n, self._A, self._B, ctypes.byref(opts), _alloc_cb,
+                                     _free_cb, None, _stream_handle(), ctypes.byref(self._h),
+                                     ctypes.byref(st))
+        _check(rc)
+        self.stats = st
+        self._outs = (CsrOut * max(n, 1))()
+
+    def run(self, views=True):
+        """Recompute every C_p; returns CsrMatrix views of the batch-owned outputs."""
+        _check(_lib.spgemm_batch_run(self._h, self._outs, _stream_handle()))
+        if not views:
+            return None
+        res = []
+        for p in range(len(self.pairs)):
+            o = self._outs[p]
+            m, nnz = int(o.rows), int(o.nnz)
+            vt = torch.float64 if o.dtype == F64 else torch.float32
+            res.append(CsrMatrix((m, int(o.cols)), _view(o.row_ptr, 4 * (m + 1), torch.int32),
+                                 _view(o.col_idx, 4 * nnz, torch.int32),
+                                 _view(o.val, vt.itemsize * nnz, vt)))
+        return res
+
+    def close(self):
+        if self._h:
+            _lib.spgemm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -47,7 +47,8 @@ def test_struct_layout_matches_c(tmp_path):
     """Compile a C probe against the header and compare sizes and offsets."""
     from paper_1504_05022_amd import lib as L
     probe = tmp_path / "probe.c"
-    fields = {"spgemm_csr": L.CsrDesc, "spgemm_options": L.Options, "spgemm_info": L.Info}
+    fields = {"spgemm_csr": L.CsrDesc, "spgemm_options": L.Options, "spgemm_info": L.Info,
+              "spgemm_batch_stats": L.BatchStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "spgemm.h"', "int main(void){"]
     for cname, ct in fields.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
