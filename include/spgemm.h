@@ -8,8 +8,10 @@
  *   stage 1  per-row upper bound u_i of nnz(c_i*) (Algorithm 2),
  *   stage 2  binning of the rows by u_i into 38 bins (Algorithm 3),
  *   stage 3  hybrid allocation of the temporary matrix C~ (u_i entries for
- *            short rows, 256 for long rows, progressive 2x growth beyond)
- *            and the per-bin insert kernels (Section 3.1, "the third stage"),
+ *            short rows, 256 for long rows, progressive 2x growth beyond;
+ *            long-row work that fits one tile writes to a place of its own
+ *            instead, so that no work-group has to allocate) and the per-bin
+ *            insert kernels (Section 3.1, "the third stage"),
  *   stage 4  arranging data: row pointers of C from the row sizes, then a
  *            copy of C~ into C (Section 3.1, "the fourth stage").
  * The output nnz is not known in advance (Section 3.1): analyze runs stages
@@ -82,9 +84,11 @@ typedef void (*spgemm_free_fn)(void *ptr, void *ctx, void *stream);
 
 /* Tuning knobs.  spgemm_default_options() gives the paper's settings
  * (Algorithm 3 thresholds, 256-entry long-row slot, 2x growth).  None of
- * them changes the structure of C; values are identical for every setting
- * except for long rows whose work is split or whose result spills out of the
- * on-chip level-1 sequence (summation order differs, within rounding). */
+ * them changes the structure of C.  Every column is summed in the order of
+ * Gustavson's algorithm (ascending j) except for long-row work that goes
+ * through the level-1 merge method (work items or output column ranges of
+ * more than 4096 entries, or seg < 0): there partial sums are added in a
+ * fixed order that may round differently. */
 typedef struct {
   /* upper row sizes of: the single-size bins (group 3, default 32), then the
    * four range bins of group 4 (defaults 64, 128, 256, 512).  Rows above the
@@ -95,8 +99,8 @@ typedef struct {
   int32_t l1_cap;       /* level-1 (LDS) sequence entries of the long-row
                            kernel, 0 = automatic                              */
   int64_t seg;          /* max products per long-row work item (rows with
-                           more are split across work-groups); 0 = automatic,
-                           < 0 = never split                                  */
+                           more are split across work-groups); 0 = automatic
+                           (1024, one wavefront), < 0 = never split          */
   int64_t pool_entries; /* initial long-row pool size in entries, 0 = auto   */
   int32_t validate;     /* nonzero: check the input CSR arrays on the device  */
   int32_t timing;       /* nonzero: record per-stage times into spgemm_info   */
@@ -228,7 +232,9 @@ int spgemm_batch_create(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
 /* Recompute every C_p (structure and values) by replaying the graph on
  * `stream`; asynchronous unless problems fall back to the plain path.  If C
  * is not NULL it receives `count` views of the outputs, which stay owned by
- * the batch (valid until spgemm_batch_destroy). */
+ * the batch: valid until spgemm_batch_destroy, except that a fallback
+ * problem receives new arrays on every run (its previous ones are released
+ * with free_fn, in stream order). */
 int spgemm_batch_run(spgemm_batch batch, spgemm_csr_out *C, void *stream);
 
 int spgemm_batch_stats_get(spgemm_batch batch, spgemm_batch_stats *stats);

@@ -67,30 +67,49 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_part(int64_t *part, int64_t nb
   if (threadIdx.x == 0) part[nb] = carry;
 }
 
-// Phase 3: rescan every tile from its offset.  Thread t owns the IPT
-// consecutive elements t*IPT .. t*IPT+IPT-1 of the tile.
+// Phase 3: rescan every tile from its offset.  Loads and stores are
+// coalesced (consecutive threads, consecutive elements); the tile goes
+// through LDS so that thread t can scan its IPT consecutive elements
+// t*IPT .. t*IPT+IPT-1 (one pad word per IPT elements keeps that access
+// spread over the banks).
+DEVI int scan_lds_ix(int i) { return i + i / SCAN_IPT; }
+
 template <typename F>
 __global__ __launch_bounds__(SCAN_NT) void k_scan_down(F f, int64_t n, const int64_t *part,
                                                        int64_t nb, int64_t *out) {
   __shared__ int64_t sm[SCAN_NT / WAVE + 1];
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE + threadIdx.x * SCAN_IPT;
+  __shared__ int64_t tile[SCAN_TILE + SCAN_TILE / SCAN_IPT];
+  const int t = threadIdx.x;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE;
+#pragma unroll
+  for (int j = 0; j < SCAN_IPT; ++j) {
+    const int i = j * SCAN_NT + t;
+    const int64_t e = base + i;
+    tile[scan_lds_ix(i)] = e < n ? f(e) : 0;
+  }
+  __syncthreads();
   int64_t v[SCAN_IPT];
   int64_t s = 0;
 #pragma unroll
   for (int j = 0; j < SCAN_IPT; ++j) {
-    const int64_t e = base + j;
-    v[j] = e < n ? f(e) : 0;
+    v[j] = tile[scan_lds_ix(t * SCAN_IPT + j)];
     s += v[j];
   }
   int64_t tot;
   int64_t ex = block_excl_sum<SCAN_NT>(s, sm, tot) + part[blockIdx.x];
 #pragma unroll
   for (int j = 0; j < SCAN_IPT; ++j) {
-    const int64_t e = base + j;
-    if (e < n) out[e] = ex;
+    tile[scan_lds_ix(t * SCAN_IPT + j)] = ex;  // the slots this thread read
     ex += v[j];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = part[nb];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < SCAN_IPT; ++j) {
+    const int i = j * SCAN_NT + t;
+    const int64_t e = base + i;
+    if (e < n) out[e] = tile[scan_lds_ix(i)];
+  }
+  if (blockIdx.x == 0 && t == 0) out[n] = part[nb];
 }
 
 template <typename F>
@@ -221,6 +240,8 @@ __global__ __launch_bounds__(256) void k_row_stats(RowStatsArgs a) {
       v[5] = ui;
       v[6] = static_cast<int64_t>(nseg) * (npiece + 1);
       v[8] = rmax;
+    } else if (ui <= kOneShot) {
+      v[5] = rmax;  // one-tile row: its result has a place of its own
     } else if (rmax > a.long_slot) {
       int64_t cap = a.long_slot;
       while (cap < rmax) cap *= 2;

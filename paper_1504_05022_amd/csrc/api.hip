@@ -324,9 +324,10 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   p->l1cap = o.l1_cap ? o.l1_cap : long_l1cap_default(dtype_bytes(p->dtype));
   // default segment: one tile of the one-pass kernel, and never more than
   // the level-1 sequence can take without spilling
-  p->lp.segp = o.seg < 0 ? -1 : (o.seg > 0 ? o.seg : std::min(p->l1cap - kLongTile, kOneShot));
+  // default segments and combine ranges fit one wavefront (kWaveTile)
+  p->lp.segp = o.seg < 0 ? -1 : (o.seg > 0 ? o.seg : kWaveTile);
   p->lp.maxs = combine_maxs();
-  p->lp.cb = 2048;
+  p->lp.cb = kWaveTile / 2;
   p->lp.minw_shift = 4;
   p->lp.maxw_shift = 30;
   const int64_t nh = static_cast<int64_t>(NBINS) * p->nwaves;
@@ -497,10 +498,14 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   const size_t osp = L.add<int32_t>(nlong > 0 ? S.n_split : 0);
   const size_t opbc = L.add<int32_t>(nlong > 0 ? S.sum_u_multi : 0);
   const size_t opbv = L.add<T>(nlong > 0 ? S.sum_u_multi : 0);
+  const size_t oobc = L.add<int32_t>(nlong > 0 ? S.sum_u_multi : 0);
+  const size_t oobv = L.add<T>(nlong > 0 ? S.sum_u_multi : 0);
   const size_t otmp = L.add<int64_t>(long_table_tmp_len(nlong));
   const size_t ocnt = L.add<LongCounters>(1);
   const size_t ogl = L.add<unsigned int>(nitems);
   const size_t ogl2 = L.add<unsigned int>(npieces);
+  const size_t ol1 = L.add<unsigned int>(nitems);
+  const size_t ol2 = L.add<unsigned int>(npieces);
   p->cws_bytes = L.bytes();
   p->cws = p->al.get(p->cws_bytes, s);
   if (!p->cws) return fail(SPGEMM_ENOMEM, "C~ allocation failed");
@@ -522,10 +527,14 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   int32_t *split = at<int32_t>(p->cws, osp);
   int32_t *pcol = at<int32_t>(p->cws, opbc);
   T *pval = at<T>(p->cws, opbv);
+  int32_t *ocol = at<int32_t>(p->cws, oobc);
+  T *oval = at<T>(p->cws, oobv);
   int64_t *lt_tmp = at<int64_t>(p->cws, otmp);
   LongCounters *lcnt = at<LongCounters>(p->cws, ocnt);
   unsigned int *glist = at<unsigned int>(p->cws, ogl);
   unsigned int *glist2 = at<unsigned int>(p->cws, ogl2);
+  unsigned int *list1 = at<unsigned int>(p->cws, ol1);
+  unsigned int *list2 = at<unsigned int>(p->cws, ol2);
 
   EscArgs<T> ea;
   ea.arp = A->row_ptr;
@@ -582,6 +591,8 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   la.partials = partials;
   la.pcol = pcol;
   la.pval = pval;
+  la.ocol = ocol;
+  la.oval = oval;
   la.split = split;
   la.pieces = pieces;
   la.piece_lrow = piece_lrow;
@@ -590,6 +601,8 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   la.cnt = lcnt;
   la.glist = glist;
   la.glist2 = glist2;
+  la.list1 = list1;
+  la.list2 = list2;
   la.ncols = p->n;
   const bool spill_expected = S.spill_bound > 0 || p->opt.pool_entries > 0;
   auto new_pool = [&](int64_t entries, unsigned long long used) -> int {
@@ -623,9 +636,10 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     launch_item_entry(A->row_ptr, p->P, items, nitems, s);
     launch_cstate_init(cstates, npieces, s);
     launch_zero(lcnt, sizeof(LongCounters), s);
-    // phase 1: every segment; one tile when small enough, else the level-1
-    // merge method
+    // phase 1: every segment; one wavefront, else one work-group tile, else
+    // the level-1 merge method
     stage_begin(p, SPGEMM_T_LONG, s);
+    launch_long_wave<T>(la, nitems, s);
     launch_long_oneshot<T>(la, nitems, s);
     if (launch_long<T>(la, nitems, p->l1cap, s))
       return fail(SPGEMM_EINVAL, "no long-row kernel for this l1_cap");
@@ -652,7 +666,8 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
       la.fail_list = fail_a;
     }
     // phase 2: every output piece of the multi-segment rows
-    if (S.sum_u_multi > 0) {
+    if (S.n_split > 0) {  // some row was split
+      launch_combine_wave<T>(la, npieces, s);
       launch_combine_oneshot<T>(la, npieces, s);
       launch_combine<T>(la, npieces, s);
     }
@@ -686,7 +701,8 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
         launch_cstate_init(cstates, npieces, s);
         launch_zero(lcnt, sizeof(LongCounters), s);
         la.fail_list2 = f2;
-        if (S.sum_u_multi > 0) {
+        if (S.n_split > 0) {  // some row was split
+          launch_combine_wave<T>(la, npieces, s);
           launch_combine_oneshot<T>(la, npieces, s);
           launch_combine<T>(la, npieces, s);
         }

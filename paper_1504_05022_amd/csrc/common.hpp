@@ -14,6 +14,14 @@ constexpr int WAVE = 64;
 
 DEVI int lane() { return static_cast<int>(__lane_id()); }
 
+// Orders the LDS accesses of one wavefront (no work-group barrier): for
+// data that only the lanes of one wavefront share.
+DEVI void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- shuffles
 
 DEVI uint32_t shfl_xor_u32(uint32_t v, int m) {

@@ -19,11 +19,13 @@ template <typename T, int G, int K, typename Key> struct EscShape {
 };
 
 // One pass of a work-group over the rows rows[base .. base + RPB) (those
-// below nrows).  LDS per row: region A holds the run starts (int32 index
+// below nrows).  A row's G lanes never leave their wavefront (G <= 64) and
+// its LDS is its own, so only wavefront-level ordering is needed: the
+// wavefronts of a work-group do not wait for each other.  LDS per row: region A holds the run starts (int32 index
 // into B's arrays, -1 = none) and later the sorted keys; region B holds a_ij
 // of each run and later the product values.  A group's lanes share one
 // wavefront, so all reads of the first use precede the writes of the second
-// in program order.  Every thread of the work-group must call it.
+// in program order.
 template <typename T, int G, int K, typename Key>
 DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
                    const int64_t nrows, unsigned char *lds) {
@@ -54,7 +56,7 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
 
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) rs[kk * G + pos] = -1;
-  __syncthreads();
+  wave_sync();
   // run starts: entry e of row i contributes products [P[e]-P[e0], P[e+1]-P[e0])
   for (int32_t e = e0 + pos; e < e1; e += G) {
     const int64_t s0 = a.P[e] - pbase;
@@ -65,7 +67,7 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
       ra[ix(static_cast<int>(s0))] = a.aval[e];
     }
   }
-  __syncthreads();
+  wave_sync();
 
   // segmented max-scan: the run containing product l starts at s(l)
   int st[K];
@@ -109,7 +111,7 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) sk[kk * G + pos] = key[kk];
   const Key pk = shfl_up_key<Key>(key[K - 1], 1);
-  __syncthreads();
+  wave_sync();
 
   // compress: count the distinct columns, place them with a group scan,
   // then fold every column's products in expansion order
@@ -146,7 +148,7 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
     }
     if (pos == 0) a.rownnz[i] = total;
   }
-  __syncthreads();
+  wave_sync();
 }
 
 }  // namespace spg

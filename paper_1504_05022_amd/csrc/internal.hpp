@@ -42,9 +42,10 @@ struct Summary {
   int64_t sum_r_long;         // sum of min(u_i, n) over long rows
   int64_t n_items;            // long-row work items
   int64_t n_pieces;           // long-row output pieces
-  int64_t sum_u_multi;        // sum of u_i over rows split into several items
+  int64_t sum_u_multi;        // output space of the one-tile paths: u_i of split rows plus
+                              // min(u_i, n) of one-item rows with u_i <= kOneShot
   int64_t n_split;            // range-start table entries (multi-item rows)
-  int64_t pool_single;        // pool entries for one-item rows' final blocks
+  int64_t pool_single;        // pool entries for final blocks of one-item rows above kOneShot
   int64_t sum_r_multi;        // sum of min(u_i, n) over multi-item rows
   int64_t spill_bound;        // sum of min(segment, n) over items that may spill L1
   int32_t err;                // nonzero: input validation failed
@@ -127,8 +128,10 @@ struct LongItem {
 
 // Work the one-tile kernels leave to the general kernels.
 struct LongCounters {
-  unsigned int glong;
-  unsigned int gcomb;
+  unsigned int glong;  // items for the general kernel
+  unsigned int gcomb;  // pieces for the general combine kernel
+  unsigned int l1;     // items for the one-tile work-group kernel
+  unsigned int l2;     // pieces for the one-tile work-group combine kernel
 };
 
 // Sorted, duplicate-free sequence in device memory.
@@ -254,13 +257,14 @@ template <typename T> struct LongArgs {
   const LongItem *items;
   const int32_t *work;    // item ids to process (nullptr: all)
   LongState *state;
-  Pool *pool;             // progressive blocks (spills, one-item rows)
-  Pool *cpool;            // combine outputs
+  Pool *pool;             // progressive blocks of the general kernels (spills, growth)
   unsigned int *fail_list;
   int32_t long_slot;
   Seq *partials;          // per item (multi-item rows)
-  int32_t *pcol;          // partial buffer
+  int32_t *pcol;          // partials of split rows / results of one-tile rows (at pbase)
   T *pval;
+  int32_t *ocol;          // results of the pieces of split rows (at pbase + range start)
+  T *oval;
   int32_t *split;         // range starts in every partial
   Piece *pieces;
   const int32_t *piece_lrow;
@@ -269,6 +273,8 @@ template <typename T> struct LongArgs {
   LongCounters *cnt;      // lengths of the two lists below
   unsigned int *glist;    // items left to the general (multi-tile) kernel
   unsigned int *glist2;   // pieces left to the general combine kernel
+  unsigned int *list1;    // items too large for one wavefront
+  unsigned int *list2;    // pieces too large for one wavefront
   int64_t ncols;
 };
 
@@ -289,6 +295,13 @@ int launch_long(const LongArgs<T> &a, int64_t nwork, int l1cap, hipStream_t s);
 // and folded in a single pass without the level-1 sequence.
 constexpr int kOneShot = 4096;
 template <typename T> void launch_long_oneshot(const LongArgs<T> &a, int64_t nitems, hipStream_t s);
+// Wavefront paths: items / pieces of at most kWaveTile entries, one
+// wavefront each; larger ones are listed for the one-tile work-group kernels,
+// which then run over those lists.
+constexpr int kWaveTile = 1024;
+template <typename T> void launch_long_wave(const LongArgs<T> &a, int64_t nitems, hipStream_t s);
+template <typename T>
+void launch_combine_wave(const LongArgs<T> &a, int64_t npieces, hipStream_t s);
 template <typename T>
 void launch_combine_oneshot(const LongArgs<T> &a, int64_t npieces, hipStream_t s);
 void launch_item_entry(const int32_t *arp, const int64_t *P, LongItem *items, int64_t n,

@@ -32,8 +32,11 @@
 // Values of items that neither spill nor are split are Gustavson's
 // sequential sums exactly; otherwise partial sums are added in segment order
 // (rounding may differ, the order is deterministic).
+#include <algorithm>
+
 #include "common.hpp"
 #include "internal.hpp"
+#include "radix.hpp"
 
 namespace spg {
 
@@ -545,6 +548,19 @@ DEVI void long_item(LongArgs<T> &a, const int32_t item_id) {
         dcol = st.gcol;
         dval = reinterpret_cast<T *>(st.gval);
         cnt = st.gcnt;
+        if (!single) {
+          // a partial always sits at its products' place, where phase 2
+          // finds it without a pointer (cnt <= the item's products)
+          int32_t *pc = a.pcol + lr.pbase + item.p0;
+          T *pv2 = a.pval + lr.pbase + item.p0;
+          for (int64_t x = t; x < cnt; x += NT) {
+            pc[x] = dcol[x];
+            pv2[x] = dval[x];
+          }
+          dcol = pc;
+          dval = pv2;
+          __syncthreads();  // the range starts are read from the copy
+        }
       }
     }
   }
@@ -629,9 +645,10 @@ DEVI void combine_piece(LongArgs<T> &a, const int32_t pid) {
 
   // segment table and the stream length
   int64_t carry = 0;
+  int64_t obase = 0;  // sum of the range starts: where this piece's result goes
   for (int32_t s0 = 0; s0 < nseg; s0 += NT) {
     const int32_t s = s0 + t;
-    int64_t len = 0;
+    int64_t len = 0, start = 0;
     if (s < nseg) {
       const Seq q = a.partials[lr.item0 + s];
       int64_t lo = 0, hi = 0;
@@ -647,11 +664,14 @@ DEVI void combine_piece(LongArgs<T> &a, const int32_t pid) {
       sg_col[s] = q.col;
       sg_val[s] = reinterpret_cast<const T *>(q.val);
       len = hi - lo;
+      start = lo;
     }
     int64_t tot;
     const int64_t ex = block_excl_sum<NT>(len, sh.scan, tot);
     if (s < nseg) sg_off[s] = static_cast<int32_t>(carry + ex);
     carry += tot;
+    block_excl_sum<NT>(start, sh.scan, tot);
+    obase += tot;
   }
   if (t == 0) sg_off[nseg] = static_cast<int32_t>(carry);
   __syncthreads();
@@ -715,29 +735,11 @@ DEVI void combine_piece(LongArgs<T> &a, const int32_t pid) {
   int64_t cnt = 0;
   if (!failed) {
     if (st.gcnt == 0) {
-      if (t == 0) {
-        sh.ok = 1;
-        int32_t *zc = nullptr;
-        T *zv = nullptr;
-        if (r == 0) {
-          sh.zcol = nullptr;
-          sh.zval = nullptr;
-        } else if (pool_alloc<T>(a.pool, static_cast<uint64_t>(r), zc, zv)) {
-          sh.zcol = zc;
-          sh.zval = zv;
-        } else {
-          sh.ok = 0;
-        }
-      }
-      __syncthreads();
-      if (sh.ok) {
-        dcol = sh.zcol;
-        dval = sh.zval;
-        if (r > 0) copy_l1<T, NT>(l1c, l1v, r, dcol, dval);
-        cnt = r;
-      } else {
-        failed = true;
-      }
+      // never spilled: L1 goes to the piece's own place (E entries)
+      dcol = a.ocol + lr.pbase + obase;
+      dval = a.oval + lr.pbase + obase;
+      if (r > 0) copy_l1<T, NT>(l1c, l1v, r, dcol, dval);
+      cnt = r;
     } else {
       if (r > 0 && !spill_l1<T, NT>(st, r, l1c, l1v, a.pool, a.long_slot, sh)) {
         failed = true;
@@ -918,35 +920,10 @@ DEVI void long1_body(LongArgs<T> &a, const int32_t item_id, const LongItem &item
   int o = static_cast<int>(block_excl_sum<NT>(static_cast<int64_t>(nh), sh.scan, rtot));
   const int r = static_cast<int>(rtot);
   const bool single = lr.nseg <= 1;
-  if (t == 0) {
-    sh.ok = 1;
-    if (!single) {
-      sh.zcol = a.pcol + lr.pbase + p0;
-      sh.zval = a.pval + lr.pbase + p0;
-    } else if (r <= a.long_slot) {
-      sh.zcol = a.e.ct_col + a.e.cto[i];
-      sh.zval = a.e.ct_val + a.e.cto[i];
-    } else {
-      int64_t cap = a.long_slot;
-      while (cap < r) cap *= 2;
-      int32_t *zc = nullptr;
-      T *zv = nullptr;
-      if (pool_alloc<T>(a.pool, static_cast<uint64_t>(cap), zc, zv)) {
-        sh.zcol = zc;
-        sh.zval = zv;
-      } else {
-        sh.ok = 0;
-      }
-    }
-  }
-  __syncthreads();
-  if (!sh.ok) {
-    // left to the general kernel, which can record a checkpoint
-    if (t == 0) a.glist[atomicAdd(&a.cnt->glong, 1u)] = static_cast<unsigned int>(item_id);
-    return;
-  }
-  int32_t *dcol = sh.zcol;
-  T *dval = sh.zval;
+  // partial of a split row at its products' place; a whole row at its own
+  // place of min(u, n) entries
+  int32_t *dcol = a.pcol + lr.pbase + (single ? 0 : p0);
+  T *dval = a.pval + lr.pbase + (single ? 0 : p0);
   int32_t ho[KT];
 #pragma unroll
   for (int kk = 0; kk < KT; ++kk) {
@@ -994,19 +971,223 @@ DEVI void long1_body(LongArgs<T> &a, const int32_t item_id, const LongItem &item
 }
 
 
+// Radix variant of the one-tile pass (column offsets fit the packed 32-bit
+// key).  A row with one segment is sorted on the column and folded in
+// sequence order straight into its destination.  A segment of a split row
+// is only partitioned by output range (stable, so every range keeps the
+// sequence order of its products): phase 2 then sorts each range once and
+// folds it in sequence order, which gives Gustavson's sums exactly.
+constexpr int kRadixBits = 8;
+
+template <typename T, int NT, int KT>
+DEVI void long1_radix(LongArgs<T> &a, const int32_t item_id, const LongItem &item, uint32_t *ka,
+                      uint32_t *kb, T *pv, uint32_t *cnt, MergeShared<T> &sh) {
+  constexpr int TILE = NT * KT;
+  constexpr int LOGT = Log2<TILE>::v;
+  constexpr int NW = NT / WAVE;
+  int32_t *rs = reinterpret_cast<int32_t *>(ka);
+  T *ra = pv;
+  const int t = threadIdx.x;
+  const int w = t / WAVE;
+  const int ln = lane();
+  const int64_t p0 = item.p0, p1 = item.p1;
+  const LongRow lr = a.lrows[item.lrow];
+  const int32_t i = item.row;
+  const int32_t e1 = a.e.arp[i + 1];
+  const int64_t pbase = a.e.P[a.e.arp[i]];
+  const int tn = static_cast<int>(p1 - p0);
+
+  // expansion: run starts, then a max-scan gives every product its run
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) rs[kk * NT + t] = -1;
+  __syncthreads();
+  for (int32_t e = item.e_first + t; e < e1; e += NT) {
+    const int64_t s0 = a.e.P[e] - pbase;
+    if (s0 >= p1) break;
+    const int64_t s1 = a.e.P[e + 1] - pbase;
+    if (s1 > p0 && s1 > s0) {
+      int64_t ls = s0 - p0;
+      int32_t off = 0;
+      if (ls < 0) {
+        off = static_cast<int32_t>(-ls);
+        ls = 0;
+      }
+      rs[tix<NT, KT>(static_cast<int>(ls))] = a.e.brp[a.e.acol[e]] + off;
+      ra[tix<NT, KT>(static_cast<int>(ls))] = a.e.aval[e];
+    }
+  }
+  __syncthreads();
+  int st_run[KT];
+  int run = -1;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    const int f = (l < tn && rs[tix<NT, KT>(l)] >= 0) ? l : -1;
+    run = max(run, f);
+    st_run[kk] = run;
+  }
+  const int before = block_excl_max<NT>(run, sh.imax);
+  int32_t col[KT];
+  T prod[KT];
+  int cmin = 0x7fffffff, cmax = -1;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    col[kk] = 0;
+    prod[kk] = T(0);
+    const int s0 = max(before, st_run[kk]);
+    if (l < tn && s0 >= 0) {
+      const int32_t bidx = rs[tix<NT, KT>(s0)] + (l - s0);
+      const T av = ra[tix<NT, KT>(s0)];
+      col[kk] = a.e.bcol[bidx];
+      prod[kk] = av * a.e.bval[bidx];
+      cmin = min(cmin, col[kk]);
+      cmax = max(cmax, col[kk]);
+    }
+  }
+  block_minmax<NT>(cmin, cmax, sh.imax);  // also orders the staging reads before the writes
+  if (tn <= 0) {
+    cmin = 0;
+    cmax = 0;
+  }
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    if (l < tn) {
+      ka[l] = (static_cast<uint32_t>(col[kk] - cmin) << LOGT) | static_cast<uint32_t>(l);
+      pv[l] = prod[kk];
+    }
+  }
+  __syncthreads();
+
+  const bool single = lr.nseg <= 1;
+  if (!single) {
+    // partition by output range; the partial keeps every product
+    const int shift = lr.shift;
+    const int32_t qlo = cmin >> shift;
+    const int bits = bit_width(static_cast<uint32_t>((cmax >> shift) - qlo));
+    const uint32_t *R = radix_sort<NT, KT, kRadixBits>(
+        ka, kb, tn, bits,
+        [&](uint32_t k) {
+          return static_cast<uint32_t>(((static_cast<int32_t>(k >> LOGT) + cmin) >> shift) - qlo);
+        },
+        cnt, sh.scan);
+    int32_t *dcol = a.pcol + lr.pbase + p0;
+    T *dval = a.pval + lr.pbase + p0;
+    const int32_t np = lr.npiece;
+    const int32_t nseg = lr.nseg;
+    const int32_t s = static_cast<int32_t>(item_id - lr.item0);
+    int32_t *pos = a.split + lr.sbase;
+    for (int e = t; e < tn; e += NT) {
+      const uint32_t k = R[e];
+      const int32_t c = static_cast<int32_t>(k >> LOGT) + cmin;
+      dcol[e] = c;
+      dval[e] = pv[k & (TILE - 1)];
+      const int32_t q = c >> shift;
+      const int32_t qp = e > 0 ? ((static_cast<int32_t>(R[e - 1] >> LOGT) + cmin) >> shift) : -1;
+      for (int32_t qq = qp + 1; qq <= q && qq < np; ++qq)
+        pos[static_cast<int64_t>(qq) * nseg + s] = e;
+      if (e == tn - 1)
+        for (int32_t qq = q + 1; qq <= np; ++qq) pos[static_cast<int64_t>(qq) * nseg + s] = tn;
+    }
+    if (tn <= 0)
+      for (int32_t qq = t; qq <= np; qq += NT) pos[static_cast<int64_t>(qq) * nseg + s] = 0;
+    if (t == 0) {
+      LongState st = a.state[item_id];
+      st.pos = p1;
+      st.status = 0;
+      a.state[item_id] = st;
+      Seq q;
+      q.col = dcol;
+      q.val = dval;
+      q.cnt = tn;
+      a.partials[item_id] = q;
+    }
+    return;
+  }
+
+  // whole row: sort on the column, fold every column in sequence order
+  const uint32_t *R = radix_sort<NT, KT, kRadixBits>(
+      ka, kb, tn, bit_width(static_cast<uint32_t>(cmax - cmin)),
+      [](uint32_t k) { return k >> LOGT; }, cnt, sh.scan);
+  const uint64_t below_mask = ln == 0 ? 0ull : (~0ull >> (WAVE - ln));
+  bool hd[KT];
+  int pre[KT];
+  int wcount = 0;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int e = (w * KT + kk) * WAVE + ln;
+    hd[kk] = e < tn && (e == 0 || (R[e - 1] >> LOGT) != (R[e] >> LOGT));
+    const uint64_t m = __ballot(hd[kk]);
+    pre[kk] = wcount + __popcll(m & below_mask);
+    wcount += __popcll(m);
+  }
+  if (ln == 0) sh.imax[w] = wcount;
+  __syncthreads();
+  int woff = 0, r = 0;
+#pragma unroll
+  for (int x = 0; x < NW; ++x) {
+    woff += x < w ? sh.imax[x] : 0;
+    r += sh.imax[x];
+  }
+  // the row's own place (min(u, n) entries), so no allocation is needed
+  int32_t *dcol = a.pcol + lr.pbase;
+  T *dval = a.pval + lr.pbase;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    if (hd[kk]) {
+      const int e = (w * KT + kk) * WAVE + ln;
+      const uint32_t k = R[e];
+      const uint32_t c = k >> LOGT;
+      T v = T(0);
+      v = v + pv[k & (TILE - 1)];
+      for (int e2 = e + 1; e2 < tn; ++e2) {
+        const uint32_t k2 = R[e2];
+        if ((k2 >> LOGT) != c) break;
+        v = v + pv[k2 & (TILE - 1)];
+      }
+      const int o = woff + pre[kk];
+      dcol[o] = static_cast<int32_t>(c) + cmin;
+      dval[o] = v;
+    }
+  }
+  if (t == 0) {
+    LongState st = a.state[item_id];
+    st.pos = p1;
+    st.status = 0;
+    a.state[item_id] = st;
+    Piece pc;
+    pc.col = dcol;
+    pc.val = dval;
+    pc.cnt = r;
+    pc.lrow = item.lrow;
+    pc.pad = 0;
+    a.pieces[lr.piece0] = pc;
+  }
+}
+
+// radix: two key buffers and the digit counters; bitonic: one key buffer
+template <int NT, int TILE, typename Key> struct Long1Lds {
+  static constexpr size_t bytes_a =
+      sizeof(Key) == 4 ? static_cast<size_t>(TILE) * 8 + RadixCounters<NT, kRadixBits>::count * 4
+                       : static_cast<size_t>(TILE) * sizeof(Key);
+};
+
 template <typename T, int NT, int TILE, typename Key>
-__global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
+DEVI void long1_item(LongArgs<T> &a, const int32_t item_id, unsigned char *s_a, T *s_b,
+                     MergeShared<T> &sh) {
   constexpr int KT = TILE / NT;
-  constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
-  __shared__ __align__(16) unsigned char s_a[TILE * KB];  // run starts / keys
-  __shared__ __align__(16) T s_b[TILE];                    // a_ij of runs / products
-  __shared__ MergeShared<T> sh;
-  const int32_t item_id = static_cast<int32_t>(blockIdx.x);
+  constexpr bool kRadix = sizeof(Key) == 4;
   const LongItem item = a.items[item_id];
   const int64_t size = item.p1 - item.p0;
   if (size > TILE) {
     if (threadIdx.x == 0)
       a.glist[atomicAdd(&a.cnt->glong, 1u)] = static_cast<unsigned int>(item_id);
+    return;
+  }
+  if constexpr (kRadix) {
+    uint32_t *ka = reinterpret_cast<uint32_t *>(s_a);
+    long1_radix<T, NT, KT>(a, item_id, item, ka, ka + TILE, s_b, ka + 2 * TILE, sh);
     return;
   }
   // the sorting network only as large as the item needs
@@ -1018,9 +1199,28 @@ __global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
     long1_body<T, NT, KT, Key>(a, item_id, item, s_a, s_b, sh);
 }
 
+// One item per work-group, or (list1 set) the items listed by the
+// wavefront kernel, in a grid-stride loop.
+template <typename T, int NT, int TILE, typename Key>
+__global__ __launch_bounds__(NT) void k_long1(LongArgs<T> a) {
+  __shared__ __align__(16) unsigned char s_a[Long1Lds<NT, TILE, Key>::bytes_a];  // run starts / keys
+  __shared__ __align__(16) T s_b[TILE];  // a_ij of runs / products
+  __shared__ MergeShared<T> sh;
+  if (a.list1 == nullptr) {
+    long1_item<T, NT, TILE, Key>(a, static_cast<int32_t>(blockIdx.x), s_a, s_b, sh);
+    return;
+  }
+  const unsigned int n = a.cnt->l1;
+  for (unsigned int w = blockIdx.x; w < n; w += gridDim.x) {
+    __syncthreads();
+    long1_item<T, NT, TILE, Key>(a, static_cast<int32_t>(a.list1[w]), s_a, s_b, sh);
+  }
+}
+
 template <typename T, int NT, int KT, typename Key, int MAXS>
 DEVI void combine1_body(LongArgs<T> &a, const int32_t pid, const int32_t lri, const int32_t c0,
-                        const int32_t nseg, const int64_t E, const int32_t *sg_off,
+                        const int32_t nseg, const int64_t E, const int64_t obase,
+                        const int32_t *sg_off,
                         const int32_t *sg_lo, const int32_t *const *sg_col,
                         const T *const *sg_val, unsigned char *s_a, T *s_b,
                         MergeShared<T> &sh) {
@@ -1078,27 +1278,9 @@ DEVI void combine1_body(LongArgs<T> &a, const int32_t pid, const int32_t lri, co
   int64_t rtot;
   int o = static_cast<int>(block_excl_sum<NT>(static_cast<int64_t>(nh), sh.scan, rtot));
   const int r = static_cast<int>(rtot);
-  if (t == 0) {
-    sh.ok = 1;
-    int32_t *zc = nullptr;
-    T *zv = nullptr;
-    if (r == 0) {
-      sh.zcol = nullptr;
-      sh.zval = nullptr;
-    } else if (pool_alloc<T>(a.pool, static_cast<uint64_t>(r), zc, zv)) {
-      sh.zcol = zc;
-      sh.zval = zv;
-    } else {
-      sh.ok = 0;
-    }
-  }
-  __syncthreads();
-  if (!sh.ok) {
-    if (t == 0) a.glist2[atomicAdd(&a.cnt->gcomb, 1u)] = static_cast<unsigned int>(pid);
-    return;
-  }
-  int32_t *dcol = sh.zcol;
-  T *dval = sh.zval;
+  const LongRow lr = a.lrows[lri];
+  int32_t *dcol = a.ocol + lr.pbase + obase;
+  T *dval = a.oval + lr.pbase + obase;
 #pragma unroll
   for (int kk = 0; kk < KT; ++kk) {
     const int l = t * KT + kk;
@@ -1131,19 +1313,149 @@ DEVI void combine1_body(LongArgs<T> &a, const int32_t pid, const int32_t lri, co
 }
 
 
-template <typename T, int NT, int TILE, typename Key, int MAXS>
-__global__ __launch_bounds__(NT) void k_combine1(LongArgs<T> a) {
-  constexpr int KT = TILE / NT;
-  constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
-  __shared__ __align__(16) unsigned char s_a[TILE * KB];
-  __shared__ __align__(16) T s_b[TILE];
-  __shared__ int32_t sg_off[MAXS + 1];
-  __shared__ int32_t sg_lo[MAXS];
-  __shared__ const int32_t *sg_col[MAXS];
-  __shared__ const T *sg_val[MAXS];
-  __shared__ MergeShared<T> sh;
+// Radix variant of the one-tile combine: the range's entries of all
+// partials, concatenated in segment order, sorted on the column (stable)
+// and folded in that order.
+template <typename T, int NT, int KT, int MAXS>
+DEVI void combine1_radix(LongArgs<T> &a, const int32_t pid, const int32_t lri, const int32_t c0,
+                         const int32_t nseg, const int64_t E, const int64_t obase,
+                         const int32_t *sg_off,
+                         const int32_t *sg_lo, const int32_t *const *sg_col,
+                         const T *const *sg_val, uint32_t *ka, uint32_t *kb, T *pv,
+                         uint32_t *cnt, MergeShared<T> &sh) {
+  constexpr int TILE = NT * KT;
+  constexpr int LOGT = Log2<TILE>::v;
+  constexpr int NW = NT / WAVE;
   const int t = threadIdx.x;
-  const int32_t pid = static_cast<int32_t>(blockIdx.x);
+  const int w = t / WAVE;
+  const int ln = lane();
+  const int tn = static_cast<int>(E);
+  int32_t col[KT];
+  T val[KT];
+  int cmin = 0x7fffffff, cmax = -1;
+  {
+    const int g0 = t * KT;
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (sg_off[mid] <= g0)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    int sgi = lo;
+#pragma unroll
+    for (int kk = 0; kk < KT; ++kk) {
+      const int l = t * KT + kk;
+      col[kk] = 0;
+      val[kk] = T(0);
+      if (l < tn) {
+        while (sgi + 1 < nseg && sg_off[sgi + 1] <= l) ++sgi;
+        const int64_t idx = sg_lo[sgi] + (l - sg_off[sgi]);
+        col[kk] = sg_col[sgi][idx] - c0;
+        val[kk] = sg_val[sgi][idx];
+        cmin = min(cmin, col[kk]);
+        cmax = max(cmax, col[kk]);
+      }
+    }
+  }
+  block_minmax<NT>(cmin, cmax, sh.imax);  // the segment tables are dead after this
+  if (tn <= 0) {
+    cmin = 0;
+    cmax = 0;
+  }
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int l = t * KT + kk;
+    if (l < tn) {
+      ka[l] = (static_cast<uint32_t>(col[kk] - cmin) << LOGT) | static_cast<uint32_t>(l);
+      pv[l] = val[kk];
+    }
+  }
+  __syncthreads();
+  const uint32_t *R = radix_sort<NT, KT, kRadixBits>(
+      ka, kb, tn, bit_width(static_cast<uint32_t>(cmax - cmin)),
+      [](uint32_t k) { return k >> LOGT; }, cnt, sh.scan);
+  const uint64_t below_mask = ln == 0 ? 0ull : (~0ull >> (WAVE - ln));
+  bool hd[KT];
+  int pre[KT];
+  int wcount = 0;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    const int e = (w * KT + kk) * WAVE + ln;
+    hd[kk] = e < tn && (e == 0 || (R[e - 1] >> LOGT) != (R[e] >> LOGT));
+    const uint64_t m = __ballot(hd[kk]);
+    pre[kk] = wcount + __popcll(m & below_mask);
+    wcount += __popcll(m);
+  }
+  if (ln == 0) sh.imax[w] = wcount;
+  __syncthreads();
+  int woff = 0, r = 0;
+#pragma unroll
+  for (int x = 0; x < NW; ++x) {
+    woff += x < w ? sh.imax[x] : 0;
+    r += sh.imax[x];
+  }
+  const LongRow lr = a.lrows[lri];
+  int32_t *dcol = a.ocol + lr.pbase + obase;
+  T *dval = a.oval + lr.pbase + obase;
+  const int32_t cb = c0 + cmin;
+#pragma unroll
+  for (int kk = 0; kk < KT; ++kk) {
+    if (hd[kk]) {
+      const int e = (w * KT + kk) * WAVE + ln;
+      const uint32_t k = R[e];
+      const uint32_t c = k >> LOGT;
+      T v = T(0);
+      v = v + pv[k & (TILE - 1)];
+      for (int e2 = e + 1; e2 < tn; ++e2) {
+        const uint32_t k2 = R[e2];
+        if ((k2 >> LOGT) != c) break;
+        v = v + pv[k2 & (TILE - 1)];
+      }
+      const int o = woff + pre[kk];
+      dcol[o] = cb + static_cast<int32_t>(c);
+      dval[o] = v;
+    }
+  }
+  if (t == 0) {
+    LongState st = a.cstate[pid];
+    st.pos = E;
+    a.cstate[pid] = st;
+    Piece pc;
+    pc.col = dcol;
+    pc.val = dval;
+    pc.cnt = r;
+    pc.lrow = lri;
+    pc.pad = 0;
+    a.pieces[pid] = pc;
+  }
+}
+
+// segment tables: (MAXS + 1) offsets, MAXS range starts, 2 MAXS pointers;
+// with radix sorting they live in the second key buffer (dead by then)
+template <int NT, int TILE, typename Key, int MAXS> struct Combine1Lds {
+  static constexpr size_t tab = (MAXS + 1) * 4 + MAXS * 4 + 2 * MAXS * sizeof(void *);
+  static constexpr size_t tab_al = (tab + 15) & ~static_cast<size_t>(15);
+  static constexpr size_t bytes_a =
+      sizeof(Key) == 4 ? static_cast<size_t>(TILE) * 8 + RadixCounters<NT, kRadixBits>::count * 4
+                       : static_cast<size_t>(TILE) * sizeof(Key) + tab_al;
+  static_assert(sizeof(Key) != 4 || tab <= static_cast<size_t>(TILE) * 4,
+                "tables exceed key buffer");
+};
+
+template <typename T, int NT, int TILE, typename Key, int MAXS>
+DEVI void combine1_piece(LongArgs<T> &a, const int32_t pid, unsigned char *s_a, T *s_b,
+                         MergeShared<T> &sh) {
+  constexpr int KT = TILE / NT;
+  constexpr bool kRadix = sizeof(Key) == 4;
+  unsigned char *tab = kRadix ? s_a + static_cast<size_t>(TILE) * 4
+                              : s_a + static_cast<size_t>(TILE) * sizeof(Key);
+  const T **sg_val = reinterpret_cast<const T **>(tab);
+  const int32_t **sg_col = reinterpret_cast<const int32_t **>(tab + MAXS * sizeof(void *));
+  int32_t *sg_off = reinterpret_cast<int32_t *>(tab + 2 * MAXS * sizeof(void *));
+  int32_t *sg_lo = sg_off + (MAXS + 1);
+  const int t = threadIdx.x;
   const int32_t lri = a.piece_lrow[pid];
   const LongRow lr = a.lrows[lri];
   if (lr.nseg <= 1) return;
@@ -1152,9 +1464,10 @@ __global__ __launch_bounds__(NT) void k_combine1(LongArgs<T> a) {
   const int32_t nseg = lr.nseg;
   const int32_t *pos_tab = a.split + lr.sbase;
   int64_t carry = 0;
+  int64_t obase = 0;  // sum of the range starts: where this piece's result goes
   for (int32_t s0 = 0; s0 < nseg; s0 += NT) {
     const int32_t s = s0 + t;
-    int64_t len = 0;
+    int64_t len = 0, start = 0;
     if (s < nseg) {
       const Seq q = a.partials[lr.item0 + s];
       int64_t lo = 0, hi = 0;
@@ -1168,11 +1481,14 @@ __global__ __launch_bounds__(NT) void k_combine1(LongArgs<T> a) {
       sg_col[s] = q.col;
       sg_val[s] = reinterpret_cast<const T *>(q.val);
       len = hi - lo;
+      start = lo;
     }
     int64_t tot;
     const int64_t ex = block_excl_sum<NT>(len, sh.scan, tot);
     if (s < nseg) sg_off[s] = static_cast<int32_t>(carry + ex);
     carry += tot;
+    block_excl_sum<NT>(start, sh.scan, tot);
+    obase += tot;
   }
   if (t == 0) sg_off[nseg] = static_cast<int32_t>(carry);
   __syncthreads();
@@ -1181,15 +1497,386 @@ __global__ __launch_bounds__(NT) void k_combine1(LongArgs<T> a) {
     if (t == 0) a.glist2[atomicAdd(&a.cnt->gcomb, 1u)] = static_cast<unsigned int>(pid);
     return;
   }
+  if constexpr (kRadix) {
+    uint32_t *ka = reinterpret_cast<uint32_t *>(s_a);
+    combine1_radix<T, NT, KT, MAXS>(a, pid, lri, c0, nseg, E, obase, sg_off, sg_lo, sg_col, sg_val, ka,
+                                    ka + TILE, s_b, ka + 2 * TILE, sh);
+    return;
+  }
   if (E <= TILE / 4)
-    combine1_body<T, NT, KT / 4, Key, MAXS>(a, pid, lri, c0, nseg, E, sg_off, sg_lo, sg_col,
+    combine1_body<T, NT, KT / 4, Key, MAXS>(a, pid, lri, c0, nseg, E, obase, sg_off, sg_lo, sg_col,
                                             sg_val, s_a, s_b, sh);
   else if (E <= TILE / 2)
-    combine1_body<T, NT, KT / 2, Key, MAXS>(a, pid, lri, c0, nseg, E, sg_off, sg_lo, sg_col,
+    combine1_body<T, NT, KT / 2, Key, MAXS>(a, pid, lri, c0, nseg, E, obase, sg_off, sg_lo, sg_col,
                                             sg_val, s_a, s_b, sh);
   else
-    combine1_body<T, NT, KT, Key, MAXS>(a, pid, lri, c0, nseg, E, sg_off, sg_lo, sg_col,
+    combine1_body<T, NT, KT, Key, MAXS>(a, pid, lri, c0, nseg, E, obase, sg_off, sg_lo, sg_col,
                                         sg_val, s_a, s_b, sh);
+}
+
+// One piece per work-group, or (list2 set) the pieces listed by the
+// wavefront kernel, in a grid-stride loop.
+template <typename T, int NT, int TILE, typename Key, int MAXS>
+__global__ __launch_bounds__(NT) void k_combine1(LongArgs<T> a) {
+  __shared__ __align__(16) unsigned char s_a[Combine1Lds<NT, TILE, Key, MAXS>::bytes_a];
+  __shared__ __align__(16) T s_b[TILE];
+  __shared__ MergeShared<T> sh;
+  if (a.list2 == nullptr) {
+    combine1_piece<T, NT, TILE, Key, MAXS>(a, static_cast<int32_t>(blockIdx.x), s_a, s_b, sh);
+    return;
+  }
+  const unsigned int n = a.cnt->l2;
+  for (unsigned int w = blockIdx.x; w < n; w += gridDim.x) {
+    __syncthreads();
+    combine1_piece<T, NT, TILE, Key, MAXS>(a, static_cast<int32_t>(a.list2[w]), s_a, s_b, sh);
+  }
+}
+
+// ------------------------------------------------------ wavefront items
+//
+// The common case of both phases fits one wavefront: an item or piece of at
+// most kWaveTile entries is sorted by one wavefront on (column, position)
+// with a register bitonic network (16 keys per lane) and never waits for
+// the other wavefronts of its work-group.  A one-item row is folded into its
+// result.  An item of a split row is only sorted: its partial keeps every
+// product, in (column, position) order, so that phase 2 sees each column's
+// products in sequence order and its sums are Gustavson's.
+
+constexpr int WAVE_NT = 256;  // four independent wavefronts per work-group
+constexpr int WAVE_K = kWaveTile / WAVE;
+
+// Element l of a wavefront tile lives at (l mod K) * 64 + l / K (lanes touch
+// consecutive words).
+template <int K> DEVI int wix(int l) { return (l & (K - 1)) * WAVE + (l >> Log2<K>::v); }
+
+template <typename T, int K, typename Key>
+DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
+                    unsigned char *lds_a, T *lds_b) {
+  constexpr int U = WAVE * K;
+  constexpr int LOGU = Log2<U>::v;
+  constexpr Key KMAX = KeyMax<Key>::v;
+  const int pos = lane();
+  int32_t *rs = reinterpret_cast<int32_t *>(lds_a);
+  Key *sk = reinterpret_cast<Key *>(lds_a);
+  T *ra = lds_b;
+  T *pv = lds_b;
+  const int64_t p0 = item.p0, p1 = item.p1;
+  const int tn = static_cast<int>(p1 - p0);
+  const LongRow lr = a.lrows[item.lrow];
+  const int32_t i = item.row;
+  const int32_t e1 = a.e.arp[i + 1];
+  const int64_t pbase = a.e.P[a.e.arp[i]];
+
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) rs[kk * WAVE + pos] = -1;
+  wave_sync();
+  // run starts of the b_j* rows that overlap [p0, p1)
+  for (int32_t e = item.e_first + pos; e < e1; e += WAVE) {
+    const int64_t s0 = a.e.P[e] - pbase;
+    if (s0 >= p1) break;
+    const int64_t s1 = a.e.P[e + 1] - pbase;
+    if (s1 > p0 && s1 > s0) {
+      int64_t ls = s0 - p0;
+      int32_t off = 0;
+      if (ls < 0) {
+        off = static_cast<int32_t>(-ls);
+        ls = 0;
+      }
+      rs[wix<K>(static_cast<int>(ls))] = a.e.brp[a.e.acol[e]] + off;
+      ra[wix<K>(static_cast<int>(ls))] = a.e.aval[e];
+    }
+  }
+  wave_sync();
+  int st[K];
+  int run = -1;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    const int f = (l < tn && rs[wix<K>(l)] >= 0) ? l : -1;
+    run = max(run, f);
+    st[kk] = run;
+  }
+  const int incl = group_incl_max<WAVE>(run);
+  int prev = __shfl_up(incl, 1, WAVE);
+  if (pos == 0) prev = -1;
+  Key key[K];
+  T prod[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    key[kk] = KMAX;
+    prod[kk] = T(0);
+    const int s0 = max(prev, st[kk]);
+    if (l < tn && s0 >= 0) {
+      const int32_t bidx = rs[wix<K>(s0)] + (l - s0);
+      const T av = ra[wix<K>(s0)];
+      const int32_t c = a.e.bcol[bidx];
+      prod[kk] = av * a.e.bval[bidx];
+      key[kk] = (static_cast<Key>(c) << LOGU) | static_cast<Key>(l);
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    if (l < tn) pv[wix<K>(l)] = prod[kk];
+  }
+  group_bitonic_sort<WAVE, K, Key>(key);
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) sk[kk * WAVE + pos] = key[kk];
+  const Key pk = shfl_up_key<Key>(key[K - 1], 1);
+  wave_sync();
+
+  if (lr.nseg > 1) {
+    // item of a split row: every product, sorted, plus the range starts
+    const int32_t s = static_cast<int32_t>(item_id - lr.item0);
+    const int shift = lr.shift;
+    const int32_t np = lr.npiece;
+    const int32_t nseg = lr.nseg;
+    int32_t *ptab = a.split + lr.sbase;
+    int32_t *dcol = a.pcol + lr.pbase + p0;
+    T *dval = a.pval + lr.pbase + p0;
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      const int l = pos * K + kk;
+      if (l < tn) {
+        const int32_t c = static_cast<int32_t>(key[kk] >> LOGU);
+        dcol[l] = c;
+        dval[l] = pv[wix<K>(static_cast<int>(key[kk] & (U - 1)))];
+        const Key before = kk > 0 ? key[kk - 1] : pk;
+        const int32_t q = c >> shift;
+        const int32_t qp = l > 0 ? (static_cast<int32_t>(before >> LOGU) >> shift) : -1;
+        for (int32_t qq = qp + 1; qq <= q && qq < np; ++qq)
+          ptab[static_cast<int64_t>(qq) * nseg + s] = l;
+        if (l == tn - 1)
+          for (int32_t qq = q + 1; qq <= np; ++qq) ptab[static_cast<int64_t>(qq) * nseg + s] = tn;
+      }
+    }
+    if (pos == 0) {
+      LongState stt = a.state[item_id];
+      stt.pos = p1;
+      stt.status = 0;
+      a.state[item_id] = stt;
+      Seq q;
+      q.col = dcol;
+      q.val = dval;
+      q.cnt = tn;
+      a.partials[item_id] = q;
+    }
+    return;
+  }
+
+  // one-item row: fold every column in position order into the row's place
+  uint32_t hmask = 0;
+  int nh = 0;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    const Key before = kk > 0 ? key[kk - 1] : pk;
+    const bool head = l < tn && (l == 0 || (before >> LOGU) != (key[kk] >> LOGU));
+    hmask |= head ? (1u << kk) : 0u;
+    nh += head ? 1 : 0;
+  }
+  const int incl_h = group_incl_sum<WAVE>(nh);
+  const int r = group_last<WAVE>(incl_h);
+  int32_t *dcol = a.pcol + lr.pbase;
+  T *dval = a.pval + lr.pbase;
+  int o = incl_h - nh;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    if (hmask & (1u << kk)) {
+      const int l = pos * K + kk;
+      const Key c = key[kk] >> LOGU;
+      T v = T(0);
+      v = v + pv[wix<K>(static_cast<int>(key[kk] & (U - 1)))];
+      for (int l2 = l + 1; l2 < tn; ++l2) {
+        const Key k2 = sk[wix<K>(l2)];
+        if ((k2 >> LOGU) != c) break;
+        v = v + pv[wix<K>(static_cast<int>(k2 & (U - 1)))];
+      }
+      dcol[o] = static_cast<int32_t>(c);
+      dval[o] = v;
+      ++o;
+    }
+  }
+  if (pos == 0) {
+    LongState stt = a.state[item_id];
+    stt.pos = p1;
+    stt.status = 0;
+    a.state[item_id] = stt;
+    Piece pc;
+    pc.col = dcol;
+    pc.val = dval;
+    pc.cnt = r;
+    pc.lrow = item.lrow;
+    pc.pad = 0;
+    a.pieces[lr.piece0] = pc;
+  }
+}
+
+template <typename T, typename Key>
+__global__ __launch_bounds__(WAVE_NT) void k_long_w(LongArgs<T> a, int64_t nitems) {
+  constexpr int NWV = WAVE_NT / WAVE;
+  constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
+  __shared__ __align__(16) unsigned char s_a[NWV][kWaveTile * KB];
+  __shared__ __align__(16) T s_b[NWV][kWaveTile];
+  const int w = threadIdx.x / WAVE;
+  const int64_t id = static_cast<int64_t>(blockIdx.x) * NWV + w;
+  if (id >= nitems) return;  // uniform across the wavefront; no work-group barriers here
+  const LongItem item = a.items[id];
+  if (item.p1 - item.p0 > kWaveTile) {
+    if (lane() == 0) a.list1[atomicAdd(&a.cnt->l1, 1u)] = static_cast<unsigned int>(id);
+    return;
+  }
+  wave_item<T, WAVE_K, Key>(a, static_cast<int32_t>(id), item, s_a[w], s_b[w]);
+}
+
+// One piece of a split row by one wavefront: the piece's range of every
+// partial, concatenated in segment order, sorted on (column, stream index),
+// folded in that order.  Larger pieces are listed for the work-group kernel.
+template <typename T, int K, typename Key, int MAXS>
+DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T *lds_b) {
+  constexpr int U = WAVE * K;
+  constexpr int LOGU = Log2<U>::v;
+  constexpr Key KMAX = KeyMax<Key>::v;
+  static_assert(2 * MAXS * 4 <= U * 4, "segment table exceeds the key buffer");
+  const int pos = lane();
+  const int32_t lri = a.piece_lrow[pid];
+  const LongRow lr = a.lrows[lri];
+  if (lr.nseg <= 1) return;
+  const int32_t b = static_cast<int32_t>(pid - lr.piece0);
+  const int32_t c0 = b << lr.shift;
+  const int32_t nseg = lr.nseg;
+  const int32_t *ptab = a.split + lr.sbase;
+  // segment table (aliases the key buffer): first stream index of every
+  // segment, and the partial-buffer index of stream index 0 for it
+  int32_t *toff = reinterpret_cast<int32_t *>(lds_a);
+  int32_t *tbase = toff + MAXS;
+  int64_t carry = 0, obase = 0;
+  for (int32_t s0 = 0; s0 < nseg; s0 += WAVE) {
+    const int32_t s = s0 + pos;
+    int64_t len = 0, lo = 0;
+    if (s < nseg) {
+      const int64_t cnt = a.partials[lr.item0 + s].cnt;
+      lo = ptab[static_cast<int64_t>(b) * nseg + s];
+      int64_t hi = ptab[static_cast<int64_t>(b + 1) * nseg + s];
+      lo = lo < 0 ? 0 : (lo > cnt ? cnt : lo);
+      hi = hi < lo ? lo : (hi > cnt ? cnt : hi);
+      len = hi - lo;
+    }
+    const int64_t incl = group_incl_sum<WAVE>(len);
+    const int64_t ex = carry + incl - len;
+    if (s < nseg) {
+      toff[s] = static_cast<int32_t>(ex < U ? ex : U);
+      tbase[s] = static_cast<int32_t>(static_cast<int64_t>(s) * lr.segp + lo - ex);
+    }
+    carry += group_last<WAVE>(incl);
+    obase += group_last<WAVE>(group_incl_sum<WAVE>(lo));
+  }
+  const int64_t E = carry;
+  if (E > U) {
+    if (pos == 0) a.list2[atomicAdd(&a.cnt->l2, 1u)] = static_cast<unsigned int>(pid);
+    return;
+  }
+  wave_sync();
+  const int tn = static_cast<int>(E);
+  const int32_t *pcol = a.pcol + lr.pbase;
+  const T *pval = a.pval + lr.pbase;
+  Key key[K];
+  T val[K];
+  {
+    const int g0 = pos * K;
+    int lo = 0, hi = nseg;  // last segment starting at or before g0
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (toff[mid] <= g0)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    int sg = lo;
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      const int l = pos * K + kk;
+      key[kk] = KMAX;
+      val[kk] = T(0);
+      if (l < tn) {
+        while (sg + 1 < nseg && toff[sg + 1] <= l) ++sg;
+        const int64_t idx = static_cast<int64_t>(tbase[sg]) + l;
+        val[kk] = pval[idx];
+        key[kk] = (static_cast<Key>(pcol[idx] - c0) << LOGU) | static_cast<Key>(l);
+      }
+    }
+  }
+  T *pv = lds_b;
+  Key *sk = reinterpret_cast<Key *>(lds_a);
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    if (l < tn) pv[wix<K>(l)] = val[kk];
+  }
+  group_bitonic_sort<WAVE, K, Key>(key);
+  wave_sync();  // the segment table is dead from here on
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) sk[kk * WAVE + pos] = key[kk];
+  const Key pk = shfl_up_key<Key>(key[K - 1], 1);
+  wave_sync();
+  uint32_t hmask = 0;
+  int nh = 0;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    const Key before = kk > 0 ? key[kk - 1] : pk;
+    const bool head = l < tn && (l == 0 || (before >> LOGU) != (key[kk] >> LOGU));
+    hmask |= head ? (1u << kk) : 0u;
+    nh += head ? 1 : 0;
+  }
+  const int incl_h = group_incl_sum<WAVE>(nh);
+  const int r = group_last<WAVE>(incl_h);
+  int32_t *dcol = a.ocol + lr.pbase + obase;
+  T *dval = a.oval + lr.pbase + obase;
+  int o = incl_h - nh;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    if (hmask & (1u << kk)) {
+      const int l = pos * K + kk;
+      const Key c = key[kk] >> LOGU;
+      T v = T(0);
+      v = v + pv[wix<K>(static_cast<int>(key[kk] & (U - 1)))];
+      for (int l2 = l + 1; l2 < tn; ++l2) {
+        const Key k2 = sk[wix<K>(l2)];
+        if ((k2 >> LOGU) != c) break;
+        v = v + pv[wix<K>(static_cast<int>(k2 & (U - 1)))];
+      }
+      dcol[o] = c0 + static_cast<int32_t>(c);
+      dval[o] = v;
+      ++o;
+    }
+  }
+  if (pos == 0) {
+    LongState stt = a.cstate[pid];
+    stt.pos = E;
+    a.cstate[pid] = stt;
+    Piece pc;
+    pc.col = dcol;
+    pc.val = dval;
+    pc.cnt = r;
+    pc.lrow = lri;
+    pc.pad = 0;
+    a.pieces[pid] = pc;
+  }
+}
+
+template <typename T, typename Key, int MAXS>
+__global__ __launch_bounds__(WAVE_NT) void k_combine_w(LongArgs<T> a, int64_t npieces) {
+  constexpr int NWV = WAVE_NT / WAVE;
+  constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
+  __shared__ __align__(16) unsigned char s_a[NWV][kWaveTile * KB];
+  __shared__ __align__(16) T s_b[NWV][kWaveTile];
+  const int w = threadIdx.x / WAVE;
+  const int64_t id = static_cast<int64_t>(blockIdx.x) * NWV + w;
+  if (id >= npieces) return;
+  wave_piece<T, WAVE_K, Key, MAXS>(a, static_cast<int32_t>(id), s_a[w], s_b[w]);
 }
 
 // Entry of A's row that contains the first product of every item.
@@ -1241,7 +1928,8 @@ DEVI LtSums lt_plan(const int32_t *binlist, int64_t off, int64_t t, int64_t nlon
   lr.segp = segp;
   z.items = nseg;
   z.pieces = npiece;
-  z.umulti = nseg > 1 ? ui : 0;
+  // output space of the one-tile paths (same rule as the analysis summary)
+  z.umulti = nseg > 1 ? ui : (ui <= kOneShot ? (ui < ncols ? ui : ncols) : 0);
   z.split = nseg > 1 ? static_cast<int64_t>(nseg) * (npiece + 1) : 0;
   return z;
 }
@@ -1399,25 +2087,50 @@ static void launch_cfg(const LongArgs<T> &a, int64_t nwork, hipStream_t s) {
                        dim3(LONG_NT), 0, s, a);
 }
 
+constexpr int64_t LIST_GRID = 1024;  // grid of the one-tile kernels over a list
+
 template <typename T> void launch_long_oneshot(const LongArgs<T> &a, int64_t nitems, hipStream_t s) {
   if (nitems <= 0) return;
+  const int64_t grid = a.list1 ? std::min<int64_t>(nitems, LIST_GRID) : nitems;
   if ((static_cast<uint64_t>(a.ncols) << Log2<kOneShot>::v) <= 0xffffffffull)
-    hipLaunchKernelGGL((k_long1<T, ONESHOT_NT, kOneShot, uint32_t>), dim3(nitems),
+    hipLaunchKernelGGL((k_long1<T, ONESHOT_NT, kOneShot, uint32_t>), dim3(grid),
                        dim3(ONESHOT_NT), 0, s, a);
   else
-    hipLaunchKernelGGL((k_long1<T, ONESHOT_NT, kOneShot, uint64_t>), dim3(nitems),
+    hipLaunchKernelGGL((k_long1<T, ONESHOT_NT, kOneShot, uint64_t>), dim3(grid),
                        dim3(ONESHOT_NT), 0, s, a);
 }
 
 template <typename T>
 void launch_combine_oneshot(const LongArgs<T> &a, int64_t npieces, hipStream_t s) {
   if (npieces <= 0) return;
+  const int64_t grid = a.list2 ? std::min<int64_t>(npieces, LIST_GRID) : npieces;
   if ((static_cast<uint64_t>(a.ncols) << Log2<kOneShot>::v) <= 0xffffffffull)
     hipLaunchKernelGGL((k_combine1<T, ONESHOT_NT, kOneShot, uint32_t, COMBINE_MAXS>),
-                       dim3(npieces), dim3(ONESHOT_NT), 0, s, a);
+                       dim3(grid), dim3(ONESHOT_NT), 0, s, a);
   else
     hipLaunchKernelGGL((k_combine1<T, ONESHOT_NT, kOneShot, uint64_t, COMBINE_MAXS>),
-                       dim3(npieces), dim3(ONESHOT_NT), 0, s, a);
+                       dim3(grid), dim3(ONESHOT_NT), 0, s, a);
+}
+
+template <typename T> void launch_long_wave(const LongArgs<T> &a, int64_t nitems, hipStream_t s) {
+  if (nitems <= 0) return;
+  const int64_t grid = (nitems + WAVE_NT / WAVE - 1) / (WAVE_NT / WAVE);
+  if ((static_cast<uint64_t>(a.ncols) << Log2<kWaveTile>::v) <= 0xffffffffull)
+    hipLaunchKernelGGL((k_long_w<T, uint32_t>), dim3(grid), dim3(WAVE_NT), 0, s, a, nitems);
+  else
+    hipLaunchKernelGGL((k_long_w<T, uint64_t>), dim3(grid), dim3(WAVE_NT), 0, s, a, nitems);
+}
+
+template <typename T>
+void launch_combine_wave(const LongArgs<T> &a, int64_t npieces, hipStream_t s) {
+  if (npieces <= 0) return;
+  const int64_t grid = (npieces + WAVE_NT / WAVE - 1) / (WAVE_NT / WAVE);
+  if ((static_cast<uint64_t>(a.ncols) << Log2<kWaveTile>::v) <= 0xffffffffull)
+    hipLaunchKernelGGL((k_combine_w<T, uint32_t, COMBINE_MAXS>), dim3(grid), dim3(WAVE_NT), 0, s,
+                       a, npieces);
+  else
+    hipLaunchKernelGGL((k_combine_w<T, uint64_t, COMBINE_MAXS>), dim3(grid), dim3(WAVE_NT), 0, s,
+                       a, npieces);
 }
 
 template <typename T>
@@ -1459,5 +2172,9 @@ template void launch_long_oneshot<float>(const LongArgs<float> &, int64_t, hipSt
 template void launch_long_oneshot<double>(const LongArgs<double> &, int64_t, hipStream_t);
 template void launch_combine_oneshot<float>(const LongArgs<float> &, int64_t, hipStream_t);
 template void launch_combine_oneshot<double>(const LongArgs<double> &, int64_t, hipStream_t);
+template void launch_long_wave<float>(const LongArgs<float> &, int64_t, hipStream_t);
+template void launch_long_wave<double>(const LongArgs<double> &, int64_t, hipStream_t);
+template void launch_combine_wave<float>(const LongArgs<float> &, int64_t, hipStream_t);
+template void launch_combine_wave<double>(const LongArgs<double> &, int64_t, hipStream_t);
 
 }  // namespace spg
