@@ -1,14 +1,18 @@
 """Benchmark: SpGEMM GFLOP/s on the irregular power-law squaring workload.
 
 One step = the whole hot path on one MI355X: analyze (upper bounds, scan,
-binning, C~ sizing) + compute (per-bin insert kernels, long-row merges,
-row pointers, allocation of C, copy into C), inputs already resident in HBM.
-Prints one JSON line (see the "metric" field); the roofline entry is for the
-dominant kernel, timed with HIP events on the library's stream during the
-timed steps.
+binning, C~ sizing) + compute (per-bin insert kernels, long-row segments and
+column ranges, row pointers, allocation of C, copy into C) + plan release,
+inputs already resident in HBM.  Prints one JSON line.  The roofline entry is
+for the dominant kernel, timed with HIP events that the library records on
+its stream during the timed steps; its algorithmic bytes are computed on the
+host from the same segment / range plan the library uses.  The batched
+(512 banded problems) and differentiable (forward + backward) forms are
+reported beside the plain path.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -23,6 +27,14 @@ METRIC = "SpGEMM GFLOP/s and % HBM roofline; batched/backward vs plain on 1 MI35
 WORKLOAD = ("irregular C=A*A, A 200000x200000 CSR, power-law row degrees "
             "(exponent 2.1, mean 16, cap 20000), uniform distinct columns, FP64 U[-1,1]")
 
+# long-row plan of the library's defaults (Algorithm 3 group 5, one-wavefront
+# segments and column ranges)
+LONG_MIN = 512
+WAVE_TILE = 1024
+MAX_SEGS = 512
+RANGE_TARGET = WAVE_TILE // 2
+MIN_SHIFT, MAX_SHIFT = 4, 30
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -30,8 +42,27 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-ext", action="store_true",
+                    help="skip the batched and differentiable forms")
     ap.add_argument("--n", type=int, default=200000, help="rows (default: the full workload)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 4 device-to-device copies of MIB MiB (the calibration "
+                         "kernel for the HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    """A plain copy kernel of known size: FETCH_SIZE / WRITE_SIZE of this
+    launch against 2 x its bytes give the counters' scale."""
+    import torch
+    x = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    for _ in range(4):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": mib << 20, "copy_probe_bytes_written": mib << 20,
+                      "launches": 4}), flush=True)
 
 
 def compulsory_bytes(A, nnz_c, s=8):
@@ -39,8 +70,173 @@ def compulsory_bytes(A, nnz_c, s=8):
     return 4 * (A.rows + 1) + A.nnz * (4 + s) + 4 * (A.rows + 1) + nnz_c * (4 + s)
 
 
+def ranges_to_index(starts, lens):
+    """Concatenation of arange(starts[k], starts[k] + lens[k])."""
+    lens = np.asarray(lens, np.int64)
+    tot = int(lens.sum())
+    if tot == 0:
+        return np.zeros(0, np.int64)
+    off = np.repeat(np.asarray(starts, np.int64) - (np.cumsum(lens) - lens), lens)
+    return off + np.arange(tot, dtype=np.int64)
+
+
+def wave_kernel_bytes(A, B, crp, cci, s):
+    """Algorithmic bytes of the two one-wavefront long-row kernels.
+
+    Segment kernel, per segment of at most WAVE_TILE products: its A entries
+    (P, column, value, B's row pointer: 16 + s bytes each), the gathered B
+    entries (4 + s each) and what it writes (the row's result for a one-
+    segment row, the segment's products plus its range starts otherwise).
+    Range kernel, per column range of a split row: the range starts and
+    partial records of every segment (32 bytes each), its entries (4 + s
+    each, only if it holds at most WAVE_TILE of them) and its result."""
+    arp = A.row_ptr.astype(np.int64)
+    brp = B.row_ptr.astype(np.int64)
+    deg = np.diff(arp)
+    bdeg = np.diff(brp)
+    n = B.cols
+    rows_of = np.repeat(np.arange(A.rows), deg)
+    w = bdeg[A.col_idx]
+    u = np.bincount(rows_of, weights=w, minlength=A.rows).astype(np.int64)
+    cnnz = np.diff(crp.astype(np.int64))
+    seg_bytes = 0
+    rng_bytes = 0
+    for i in np.nonzero(u > LONG_MIN)[0]:
+        ui = int(u[i])
+        e0, e1 = int(arp[i]), int(arp[i + 1])
+        lens = w[e0:e1]
+        starts = np.cumsum(lens) - lens
+        ends = starts + lens
+        if ui <= WAVE_TILE:
+            seg_bytes += (e1 - e0) * (16 + s) + ui * (4 + s) + int(cnnz[i]) * (4 + s) + 128
+            continue
+        segp = max(WAVE_TILE, -(-ui // MAX_SEGS))
+        if segp > WAVE_TILE:
+            continue  # not a one-wavefront row
+        nseg = -(-ui // segp)
+        wdt = -(-(n * RANGE_TARGET) // ui)
+        shift = min(max(int(math.ceil(math.log2(max(wdt, 1)))), MIN_SHIFT), MAX_SHIFT)
+        npiece = -(-n // (1 << shift))
+        p0 = np.arange(nseg, dtype=np.int64) * segp
+        p1 = np.minimum(p0 + segp, ui)
+        d_seg = np.searchsorted(starts, p1, "left") - np.searchsorted(ends, p0, "right")
+        seg_bytes += int(d_seg.sum()) * (16 + s) + 2 * ui * (4 + s) + nseg * ((npiece + 1) * 4 + 128)
+        js = A.col_idx[e0:e1]
+        cols = B.col_idx[ranges_to_index(brp[js], bdeg[js])]
+        E = np.bincount(cols >> shift, minlength=npiece)
+        r = np.bincount(cci[int(crp[i]):int(crp[i + 1])] >> shift, minlength=npiece)
+        small = E <= WAVE_TILE
+        rng_bytes += npiece * nseg * 32 + int((E[small] + r[small]).sum()) * (4 + s) + npiece * 64
+    return seg_bytes, rng_bytes
+
+
+def memory_accounting(A, crp, info, s):
+    """Temporary storage of the product under the three allocation schemes
+    the paper compares (precise nnz(c_i); hybrid: the Algorithm 3 sizes plus
+    2x growth of a long row's 256-entry slot until its result fits; upper
+    bound u_i), in MB of (column, value) entries, next to the device scratch
+    this implementation held (analysis + C~ + long-row space + pool)."""
+    arp = A.row_ptr.astype(np.int64)
+    deg = np.diff(arp)
+    u = np.bincount(np.repeat(np.arange(A.rows), deg), weights=deg[A.col_idx],
+                    minlength=A.rows).astype(np.int64)
+    cn = np.diff(crp.astype(np.int64))
+    long_rows = u > LONG_MIN
+    grow = cn[long_rows]
+    cap = np.where(grow > 256, 256 * 2.0 ** np.ceil(np.log2(np.maximum(grow, 1) / 256.0)), 0)
+    mb = (4 + s) / 1e6
+    precise = int(cn.sum())
+    hybrid = int(info.nnz_tilde) + int(cap.sum())
+    upper = int(info.nnz_hat)
+    return {"precise_MB": round(precise * mb, 1), "hybrid_MB": round(hybrid * mb, 1),
+            "upper_bound_MB": round(upper * mb, 1),
+            "hybrid_over_precise": round(hybrid / max(precise, 1), 3),
+            "upper_over_precise": round(upper / max(precise, 1), 3),
+            "this_implementation_scratch_MB": round(int(info.bytes_scratch) / 1e6, 1)}
+
+
+def extensions(args, torch, S, L):
+    """Batched (workload 4) and differentiable (workload 5) forms against the
+    plain path on the same GPU."""
+    out = {}
+    reps = 5
+    # ---- batched: 512 banded problems, mixed binary32 / binary64
+    try:
+        probs = S.config4()
+        dev = [(L.CsrMatrix.from_host(a), L.CsrMatrix.from_host(b)) for a, b in probs]
+        del probs
+        torch.cuda.synchronize()
+        b = L.Batch(dev)
+        st = b.stats.as_dict()
+        b.run(views=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.run(views=False)
+        torch.cuda.synchronize()
+        bms = (time.perf_counter() - t0) * 1e3 / reps
+        b.close()
+        # the same problems one plain call after another
+        for a_, b_ in dev[:8]:
+            L.spgemm(a_, b_)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a_, b_ in dev:
+            C = L.spgemm(a_, b_)
+            del C
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - t0) * 1e3
+        del dev
+        out["batched"] = {
+            "workload": "512 banded problems, n log-uniform in [1024, 65536], 4-32 nnz/row "
+                        "in a 5% band, FP64 even / FP32 odd",
+            "ms_per_run": round(bms, 3), "gflops": round(st["flops"] / (bms * 1e-3) / 1e9, 2),
+            "plain_sequential_ms": round(pms, 3),
+            "plain_gflops": round(st["flops"] / (pms * 1e-3) / 1e9, 2),
+            "speedup_vs_plain": round(pms / bms, 3), "flops": st["flops"], "nnz_c": st["nnz_c"],
+            "fallback": st["fallback"], "bin_edges": st["bin_edges"],
+            "tune_ms": [round(x, 3) for x in st["tune_ms"]]}
+    except Exception as e:  # reported, not fatal to the headline number
+        out["batched"] = {"error": repr(e)[:300]}
+    torch.cuda.empty_cache()
+    # ---- differentiable: A 500000^2 power law x B 500000x4096, binary32
+    try:
+        A, B = S.config5()
+        dA, dB = L.CsrMatrix.from_host(A), L.CsrMatrix.from_host(B)
+        del A, B
+        plan = L.Plan(dA, dB)
+        C = plan.compute()
+        dc = torch.randn(C.nnz, dtype=torch.float32, device="cuda")
+        plan.backward(C, dc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            C = L.spgemm(dA, dB)
+        torch.cuda.synchronize()
+        fms = (time.perf_counter() - t0) * 1e3 / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.backward(C, dc)
+        torch.cuda.synchronize()
+        bwms = (time.perf_counter() - t0) * 1e3 / reps
+        fl = int(plan.info.flops)
+        plan.close()
+        out["backward"] = {
+            "workload": "A 500000^2 power law (2.2, mean 20) x B 500000x4096 (32/row), FP32 N(0,1)",
+            "forward_ms": round(fms, 3), "forward_gflops": round(fl / (fms * 1e-3) / 1e9, 2),
+            "backward_ms": round(bwms, 3),
+            "backward_gflops": round(2 * fl / (bwms * 1e-3) / 1e9, 2),
+            "backward_over_forward": round(bwms / fms, 3), "flops_forward": fl}
+    except Exception as e:
+        out["backward"] = {"error": repr(e)[:300]}
+    return out
+
+
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -48,41 +244,35 @@ def main():
     import torch
 
     import synthetic as S
-    from paper_1504_05022_amd import CsrMatrix, Plan, lib
+    from paper_1504_05022_amd import lib as L
 
-    lib.load()
+    L.load()
     torch.cuda.set_device(0)
     A, _ = S.config2(n=args.n) if args.n != 200000 else S.config2()
-    dA = CsrMatrix.from_host(A)
+    dA = L.CsrMatrix.from_host(A)
     torch.cuda.synchronize()
     s = 8
 
-    # host-side per-row counts for the per-kernel byte model
-    arp = A.row_ptr.astype(np.int64)
-    deg = np.diff(arp)
-    rowlen = deg  # A*A: row lengths of B are A's
-    u = np.zeros(A.rows, np.int64)
-    np.add.at(u, np.repeat(np.arange(A.rows), deg), rowlen[A.col_idx])
-
-    def step(timing):
-        plan = Plan(dA, dA, timing=timing)
+    def step():
+        plan = L.Plan(dA, dA, timing=1)
         C = plan.compute()
         info = plan.info
         plan.close()
         return C, info
 
     for _ in range(args.warmup):
-        C, info = step(1)
+        C, info = step()
     torch.cuda.synchronize()
-    cnnz = np.diff(C.row_ptr.cpu().numpy().astype(np.int64))
+    crp = C.row_ptr.cpu().numpy()
+    cci = C.col_idx.cpu().numpy()
     nnz_c = int(C.nnz)
     del C
 
-    stage_ms = np.zeros(8)
+    stage_ms = np.zeros(L.NSTAGES)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        C, info = step(1)
+        C, info = step()
         stage_ms += np.array(list(info.stage_ms))
         del C
     torch.cuda.synchronize()
@@ -92,15 +282,16 @@ def main():
     flops = int(info.flops)
     gflops = flops / (ms * 1e-3) / 1e9
     bytes_comp = compulsory_bytes(A, nnz_c, s)
+    stages = dict(zip(L.STAGES, [round(float(x), 4) for x in stage_ms]))
 
-    # dominant kernel: the long-row merge kernel (one launch per step)
-    long_rows = u > 512
-    long_bytes = (int(np.sum(8 + deg[long_rows] * (4 + s)))          # its rows of A
-                  + 4 * (A.rows + 1) + A.nnz * (4 + s)                  # B, read once
-                  + int(np.sum(cnnz[long_rows])) * (4 + s))             # its output rows
-    long_ms = float(stage_ms[4])
-    stages = dict(zip(lib.STAGES, [round(float(x), 4) for x in stage_ms]))
-    achieved = long_bytes / (long_ms * 1e-3) / 1e9 if long_ms > 0 else 0.0
+    # dominant kernel: the longer of the two one-wavefront long-row kernels
+    seg_bytes, rng_bytes = wave_kernel_bytes(A, A, crp, cci, s)
+    cand = [("k_long_w (long-row segments, one wavefront each)", seg_bytes,
+             stages["long_wave"]),
+            ("k_combine_w (column ranges of split rows, one wavefront each)", rng_bytes,
+             stages["combine_wave"])]
+    name, kbytes, kms = max(cand, key=lambda c: c[2])
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
 
     out = {
         "metric": METRIC,
@@ -117,16 +308,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "m": A.rows, "nnz_A": A.nnz, "flops": flops,
                    "nnz_C": nnz_c, "max_u": int(info.max_u),
-                   "long_rows": int(long_rows.sum())},
+                   "long_rows": int(info.bin_count[37])},
         "hbm_compulsory": {"bytes": bytes_comp,
                            "achieved_GBps": round(bytes_comp / (ms * 1e-3) / 1e9, 2),
                            "frac": round(bytes_comp / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)},
         "stage_ms": stages,
-        "roofline": {"kernel": "k_long (long-row merge method)", "bound": "hbm",
-                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": {"kernel": name, "bound": "hbm", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                     "algorithmic_bytes": long_bytes, "kernel_ms": round(long_ms, 4)},
+                     "algorithmic_bytes": int(kbytes), "kernel_ms": round(kms, 4)},
     }
+    out["memory"] = memory_accounting(A, crp, info, s)
     if not args.no_cpu:
         import oracle
         # the oracle as it stands, single thread, on the whole workload
@@ -136,6 +328,11 @@ def main():
         out["cpu_baseline"] = {"value": round(ref.flops / dt / 1e9, 5), "unit": "GFLOP/s",
                                "cores": 1, "kind": "oracle",
                                "sample": "the full workload once (%.1f s)" % dt}
+        del ref
+    if not args.no_ext:
+        del dA
+        torch.cuda.empty_cache()
+        out["extensions"] = extensions(args, torch, S, L)
     print(json.dumps(out), flush=True)
 
 

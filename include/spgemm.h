@@ -107,7 +107,7 @@ typedef struct {
 } spgemm_options;
 
 #define SPGEMM_NBINS 38
-#define SPGEMM_NSTAGES 8
+#define SPGEMM_NSTAGES 12
 
 /* Per-stage timer slots of spgemm_info.stage_ms (options.timing != 0). */
 enum {
@@ -118,7 +118,11 @@ enum {
   SPGEMM_T_LONG = 4,    /* stage 3: long rows (all relaunch rounds)          */
   SPGEMM_T_SCAN = 5,    /* stage 4: row pointers of C                        */
   SPGEMM_T_COPY = 6,    /* stage 4: copy C~ into C                           */
-  SPGEMM_T_BACKWARD = 7 /* backward kernels                                  */
+  SPGEMM_T_BACKWARD = 7,/* backward kernels (not read back by compute)       */
+  SPGEMM_T_LONG_WAVE = 8,    /* inside LONG: the one-wavefront segment kernel */
+  SPGEMM_T_COMBINE = 9,      /* stage 3: column ranges of split long rows     */
+  SPGEMM_T_COMBINE_WAVE = 10,/* inside COMBINE: the one-wavefront range kernel*/
+  SPGEMM_T_RESERVED = 11
 };
 
 typedef struct {
@@ -135,7 +139,7 @@ typedef struct {
   int64_t pool_used;    /* entries taken from the pool                       */
   int32_t realloc_rounds; /* pool exhaustions handled by relaunching         */
   int32_t reserved;
-  float stage_ms[SPGEMM_NSTAGES];
+  float stage_ms[SPGEMM_NSTAGES]; /* 0 for stages that did not run        */
   float long_kernel_ms; /* summed duration of the long-row kernel launches   */
   int32_t long_launches;
 } spgemm_info;

@@ -197,6 +197,7 @@ struct spgemm_plan_s {
   spgemm_info info{};
   hipEvent_t ev[2 * SPGEMM_NSTAGES] = {};
   bool events = false;
+  uint32_t stage_mask = 0;  // stages recorded since the last read-back
   std::vector<hipEvent_t> long_ev;
 };
 
@@ -271,7 +272,9 @@ int check_options(const spgemm_options &o) {
 }
 
 void stage_begin(spgemm_plan p, int st, hipStream_t s) {
-  if (p->events) (void)hipEventRecord(p->ev[2 * st], s);
+  if (!p->events) return;
+  (void)hipEventRecord(p->ev[2 * st], s);
+  p->stage_mask |= 1u << st;
 }
 void stage_end(spgemm_plan p, int st, hipStream_t s) {
   if (p->events) (void)hipEventRecord(p->ev[2 * st + 1], s);
@@ -639,7 +642,9 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     // phase 1: every segment; one wavefront, else one work-group tile, else
     // the level-1 merge method
     stage_begin(p, SPGEMM_T_LONG, s);
+    stage_begin(p, SPGEMM_T_LONG_WAVE, s);
     launch_long_wave<T>(la, nitems, s);
+    stage_end(p, SPGEMM_T_LONG_WAVE, s);
     launch_long_oneshot<T>(la, nitems, s);
     if (launch_long<T>(la, nitems, p->l1cap, s))
       return fail(SPGEMM_EINVAL, "no long-row kernel for this l1_cap");
@@ -667,9 +672,13 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     }
     // phase 2: every output piece of the multi-segment rows
     if (S.n_split > 0) {  // some row was split
+      stage_begin(p, SPGEMM_T_COMBINE, s);
+      stage_begin(p, SPGEMM_T_COMBINE_WAVE, s);
       launch_combine_wave<T>(la, npieces, s);
+      stage_end(p, SPGEMM_T_COMBINE_WAVE, s);
       launch_combine_oneshot<T>(la, npieces, s);
       launch_combine<T>(la, npieces, s);
+      stage_end(p, SPGEMM_T_COMBINE, s);
     }
     finish_long();
   }
@@ -721,6 +730,10 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   if (nnz >= (int64_t(1) << 31)) return fail(SPGEMM_EOVERFLOW, "nnz(C) exceeds 2^31 - 1");
   I.pool_used = nlong > 0 ? static_cast<int64_t>(p->hstat->pool_used) : 0;
   I.pool_entries = pool_entries;
+  // device scratch held now: analysis, C~ and long-row tables, pool chunks
+  I.bytes_scratch = static_cast<int64_t>(p->ws_bytes + p->cws_bytes);
+  for (int64_t e = pool_entries, k = 0; k <= I.realloc_rounds && nlong > 0; ++k, e /= 2)
+    I.bytes_scratch += static_cast<int64_t>(pool_chunk_bytes(e, sizeof(T)));
 
   // ---- stage 4b: allocate C and copy C~ into it
   void *crp = p->al.get(static_cast<size_t>(m + 1) * 4, s);
@@ -793,8 +806,15 @@ extern "C" int spgemm_compute(spgemm_plan plan, const spgemm_csr *A, const spgem
   }
   if (p->events) {
     HIP_TRY(hipEventSynchronize(p->ev[2 * SPGEMM_T_COPY + 1]));
-    for (int st = SPGEMM_T_TINY; st <= SPGEMM_T_COPY; ++st)
-      (void)hipEventElapsedTime(&p->info.stage_ms[st], p->ev[2 * st], p->ev[2 * st + 1]);
+    static const int kComputeStages[] = {SPGEMM_T_TINY,   SPGEMM_T_MEDIUM,    SPGEMM_T_LONG,
+                                         SPGEMM_T_SCAN,   SPGEMM_T_COPY,      SPGEMM_T_LONG_WAVE,
+                                         SPGEMM_T_COMBINE, SPGEMM_T_COMBINE_WAVE};
+    for (int st : kComputeStages) {
+      p->info.stage_ms[st] = 0.f;
+      if (p->stage_mask & (1u << st))
+        (void)hipEventElapsedTime(&p->info.stage_ms[st], p->ev[2 * st], p->ev[2 * st + 1]);
+    }
+    p->stage_mask = 0;
     p->info.long_kernel_ms = p->info.stage_ms[SPGEMM_T_LONG];
   }
   if (info) *info = p->info;

@@ -83,27 +83,52 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
   int prev = __shfl_up(incl, 1, WAVE);
   if (pos == 0) prev = -1;
 
+  // B index and a_ij of every product, resolved in this lane-blocked order
+  // and handed over through LDS, so that the gather below reads consecutive
+  // products with consecutive lanes (coalesced loads along each b_j* row)
+  int32_t gbx[K];
+  T gav[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    const int s0 = max(prev, st[kk]);
+    const bool ok = l < u && s0 >= 0;
+    gbx[kk] = ok ? rs[ix(s0)] + (l - s0) : 0;
+    gav[kk] = ok ? ra[ix(s0)] : T(0);
+  }
+  int32_t *gb = rs;  // product l at gb[l] / ga[l]
+  T *ga = ra;
+  wave_sync();
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    if (l < u) {
+      gb[l] = gbx[kk];
+      ga[l] = gav[kk];
+    }
+  }
+  wave_sync();
   Key key[K];
   T prod[K];
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
-    const int l = pos * K + kk;
+    const int l = kk * G + pos;
     key[kk] = KMAX;
     prod[kk] = T(0);
-    const int s0 = max(prev, st[kk]);
-    if (l < u && s0 >= 0) {
-      const int32_t bidx = rs[ix(s0)] + (l - s0);
-      const T av = ra[ix(s0)];
+    if (l < u) {
+      const int32_t bidx = gb[l];
+      const T av = ga[l];
       const int32_t c = a.bcol[bidx];
       const T bv = a.bval[bidx];
       prod[kk] = av * bv;
       key[kk] = (static_cast<Key>(c) << LOGU) | static_cast<Key>(l);
     }
   }
+  wave_sync();  // pv takes the place of ga
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
-    const int l = pos * K + kk;
-    if (l < u) pv[ix(l)] = prod[kk];
+    const int l = kk * G + pos;
+    if (l < u) pv[l] = prod[kk];
   }
 
   group_bitonic_sort<G, K, Key>(key);
@@ -135,11 +160,11 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
         const int l = pos * K + kk;
         const Key c = key[kk] >> LOGU;
         T v = T(0);
-        v = v + pv[ix(static_cast<int>(key[kk] & (U - 1)))];
+        v = v + pv[static_cast<int>(key[kk] & (U - 1))];
         for (int l2 = l + 1; l2 < u; ++l2) {
           const Key k2 = sk[ix(l2)];
           if ((k2 >> LOGU) != c) break;
-          v = v + pv[ix(static_cast<int>(k2 & (U - 1)))];
+          v = v + pv[static_cast<int>(k2 & (U - 1))];
         }
         a.ct_col[o] = static_cast<int32_t>(c);
         a.ct_val[o] = v;

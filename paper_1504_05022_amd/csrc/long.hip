@@ -1599,27 +1599,50 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
   const int incl = group_incl_max<WAVE>(run);
   int prev = __shfl_up(incl, 1, WAVE);
   if (pos == 0) prev = -1;
-  Key key[K];
-  T prod[K];
+  // B index and a_ij of every product, resolved in lane-blocked order and
+  // handed over through LDS so that consecutive lanes gather consecutive
+  // products (coalesced loads along each b_j* row)
+  int32_t gbx[K];
+  T gav[K];
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     const int l = pos * K + kk;
-    key[kk] = KMAX;
-    prod[kk] = T(0);
     const int s0 = max(prev, st[kk]);
-    if (l < tn && s0 >= 0) {
-      const int32_t bidx = rs[wix<K>(s0)] + (l - s0);
-      const T av = ra[wix<K>(s0)];
-      const int32_t c = a.e.bcol[bidx];
-      prod[kk] = av * a.e.bval[bidx];
-      key[kk] = (static_cast<Key>(c) << LOGU) | static_cast<Key>(l);
-    }
+    const bool ok = l < tn && s0 >= 0;
+    gbx[kk] = ok ? rs[wix<K>(s0)] + (l - s0) : 0;
+    gav[kk] = ok ? ra[wix<K>(s0)] : T(0);
   }
+  int32_t *gb = rs;  // product l at gb[l] / ga[l]
+  T *ga = ra;
   wave_sync();
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     const int l = pos * K + kk;
-    if (l < tn) pv[wix<K>(l)] = prod[kk];
+    if (l < tn) {
+      gb[l] = gbx[kk];
+      ga[l] = gav[kk];
+    }
+  }
+  wave_sync();
+  Key key[K];
+  T prod[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = kk * WAVE + pos;
+    key[kk] = KMAX;
+    prod[kk] = T(0);
+    if (l < tn) {
+      const int32_t bidx = gb[l];
+      const int32_t c = a.e.bcol[bidx];
+      prod[kk] = ga[l] * a.e.bval[bidx];
+      key[kk] = (static_cast<Key>(c) << LOGU) | static_cast<Key>(l);
+    }
+  }
+  wave_sync();  // pv takes the place of ga
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = kk * WAVE + pos;
+    if (l < tn) pv[l] = prod[kk];
   }
   group_bitonic_sort<WAVE, K, Key>(key);
 #pragma unroll
@@ -1642,7 +1665,7 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
       if (l < tn) {
         const int32_t c = static_cast<int32_t>(key[kk] >> LOGU);
         dcol[l] = c;
-        dval[l] = pv[wix<K>(static_cast<int>(key[kk] & (U - 1)))];
+        dval[l] = pv[static_cast<int>(key[kk] & (U - 1))];
         const Key before = kk > 0 ? key[kk - 1] : pk;
         const int32_t q = c >> shift;
         const int32_t qp = l > 0 ? (static_cast<int32_t>(before >> LOGU) >> shift) : -1;
@@ -1688,11 +1711,11 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
       const int l = pos * K + kk;
       const Key c = key[kk] >> LOGU;
       T v = T(0);
-      v = v + pv[wix<K>(static_cast<int>(key[kk] & (U - 1)))];
+      v = v + pv[static_cast<int>(key[kk] & (U - 1))];
       for (int l2 = l + 1; l2 < tn; ++l2) {
         const Key k2 = sk[wix<K>(l2)];
         if ((k2 >> LOGU) != c) break;
-        v = v + pv[wix<K>(static_cast<int>(k2 & (U - 1)))];
+        v = v + pv[static_cast<int>(k2 & (U - 1))];
       }
       dcol[o] = static_cast<int32_t>(c);
       dval[o] = v;
@@ -1782,8 +1805,10 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
   const int tn = static_cast<int>(E);
   const int32_t *pcol = a.pcol + lr.pbase;
   const T *pval = a.pval + lr.pbase;
-  Key key[K];
-  T val[K];
+  // partial-buffer index of every stream entry, found in lane-blocked order
+  // (one search, then a walk) and handed over through LDS so that the loads
+  // below read consecutive entries with consecutive lanes
+  int32_t gix[K];
   {
     const int g0 = pos * K;
     int lo = 0, hi = nseg;  // last segment starting at or before g0
@@ -1798,25 +1823,36 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) {
       const int l = pos * K + kk;
-      key[kk] = KMAX;
-      val[kk] = T(0);
+      gix[kk] = 0;
       if (l < tn) {
         while (sg + 1 < nseg && toff[sg + 1] <= l) ++sg;
-        const int64_t idx = static_cast<int64_t>(tbase[sg]) + l;
-        val[kk] = pval[idx];
-        key[kk] = (static_cast<Key>(pcol[idx] - c0) << LOGU) | static_cast<Key>(l);
+        gix[kk] = tbase[sg] + l;
       }
     }
   }
-  T *pv = lds_b;
-  Key *sk = reinterpret_cast<Key *>(lds_a);
+  int32_t *gi = reinterpret_cast<int32_t *>(lds_a);
+  wave_sync();  // the segment table is dead from here on
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     const int l = pos * K + kk;
-    if (l < tn) pv[wix<K>(l)] = val[kk];
+    if (l < tn) gi[l] = gix[kk];
   }
+  wave_sync();
+  Key key[K];
+  T *pv = lds_b;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = kk * WAVE + pos;
+    key[kk] = KMAX;
+    if (l < tn) {
+      const int64_t idx = gi[l];
+      pv[l] = pval[idx];
+      key[kk] = (static_cast<Key>(pcol[idx] - c0) << LOGU) | static_cast<Key>(l);
+    }
+  }
+  Key *sk = reinterpret_cast<Key *>(lds_a);
   group_bitonic_sort<WAVE, K, Key>(key);
-  wave_sync();  // the segment table is dead from here on
+  wave_sync();  // gi is dead from here on
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) sk[kk * WAVE + pos] = key[kk];
   const Key pk = shfl_up_key<Key>(key[K - 1], 1);
@@ -1842,11 +1878,11 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
       const int l = pos * K + kk;
       const Key c = key[kk] >> LOGU;
       T v = T(0);
-      v = v + pv[wix<K>(static_cast<int>(key[kk] & (U - 1)))];
+      v = v + pv[static_cast<int>(key[kk] & (U - 1))];
       for (int l2 = l + 1; l2 < tn; ++l2) {
         const Key k2 = sk[wix<K>(l2)];
         if ((k2 >> LOGU) != c) break;
-        v = v + pv[wix<K>(static_cast<int>(k2 & (U - 1)))];
+        v = v + pv[static_cast<int>(k2 & (U - 1))];
       }
       dcol[o] = c0 + static_cast<int32_t>(c);
       dval[o] = v;

@@ -18,8 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libspgemm.so")
 
 F32, F64 = 0, 1
 NBINS = 38
-NSTAGES = 8
-STAGES = ("upper", "bin", "tiny", "medium", "long", "scan", "copy", "backward")
+NSTAGES = 12
+STAGES = ("upper", "bin", "tiny", "medium", "long", "scan", "copy", "backward", "long_wave",
+          "combine", "combine_wave", "reserved")
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EOVERFLOW", -4: "EHIP", -5: "ESTATE"}
 
