@@ -634,9 +634,8 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
                        ? p->opt.pool_entries
                        : S.pool_single + S.sum_r_multi + 3 * S.spill_bound + 65536;
     if ((rc = new_pool(pool_entries, 0)) != SPGEMM_OK) return rc;
-    launch_long_table(p->binlist, S.bin_off[LONG_BIN], nlong, p->u, p->n, p->lp, lrows, items,
-                      states, partials, piece_lrow, lt_tmp, s);
-    launch_item_entry(A->row_ptr, p->P, items, nitems, s);
+    launch_long_table(p->binlist, S.bin_off[LONG_BIN], nlong, p->u, p->n, p->lp, lrows, nitems,
+                      items, states, partials, npieces, piece_lrow, A->row_ptr, p->P, lt_tmp, s);
     launch_cstate_init(cstates, npieces, s);
     launch_zero(lcnt, sizeof(LongCounters), s);
     // phase 1: every segment; one wavefront, else one work-group tile, else
@@ -832,6 +831,68 @@ extern "C" int spgemm_plan_destroy(spgemm_plan plan) {
   return SPGEMM_OK;
 }
 
+namespace {
+
+// A's transposed pattern (rows of every column, ascending), built once per plan.
+int ensure_transpose(spgemm_plan p, const spgemm_csr *A, hipStream_t s) {
+  if (p->bws) return SPGEMM_OK;
+  Layout L;
+  const size_t oc = L.add<int32_t>(p->k);
+  const size_t ot = L.add<int64_t>(p->k + 1);
+  const size_t orr = L.add<int32_t>(p->nnzA);
+  const size_t op = L.add<int32_t>(p->nnzA);
+  const size_t opa = L.add<int64_t>(scan_part_len(std::max<int64_t>(p->k, 1)));
+  p->bws = p->al.get(L.bytes(), s);
+  if (!p->bws) return fail(SPGEMM_ENOMEM, "backward scratch allocation failed");
+  p->tcnt = at<int32_t>(p->bws, oc);
+  p->tptr = at<int64_t>(p->bws, ot);
+  p->trow = at<int32_t>(p->bws, orr);
+  p->tpos = at<int32_t>(p->bws, op);
+  p->tpart = at<int64_t>(p->bws, opa);
+  p->info.bytes_scratch += static_cast<int64_t>(L.bytes());
+  launch_transpose_pattern(A->row_ptr, A->col_idx, p->m, p->k, p->nnzA, p->tcnt, p->tptr,
+                           p->trow, p->tpos, p->tpart, s);
+  return SPGEMM_OK;
+}
+
+// Products of the dB sums are staged when they fit this budget (bytes);
+// beyond it dB is gathered with binary searches instead.
+constexpr int64_t kMaxStagedProducts = int64_t(1) << 36;
+
+template <typename T>
+int backward_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, const spgemm_csr *C,
+               void *dA_val, void *dB_val, hipStream_t s) {
+  const bool want_a = dA_val && p->nnzA > 0;
+  const bool want_b = dB_val && p->nnzB > 0;
+  if (!want_a && !want_b) return SPGEMM_OK;
+  const T *aval = static_cast<const T *>(A->val);
+  const T *bval = static_cast<const T *>(B->val);
+  const T *dc = static_cast<const T *>(C->val);
+  T *dA = want_a ? static_cast<T *>(dA_val) : nullptr;
+  T *dB = want_b ? static_cast<T *>(dB_val) : nullptr;
+  int rc;
+  if (want_b && (rc = ensure_transpose(p, A, s)) != SPGEMM_OK) return rc;
+  const int64_t nprod = p->info.nnz_hat;
+  T *W = nullptr;
+  if (want_b && nprod > 0 && nprod * static_cast<int64_t>(sizeof(T)) <= kMaxStagedProducts)
+    W = static_cast<T *>(p->al.get(static_cast<size_t>(nprod) * sizeof(T), s));
+  if (want_a || W)
+    launch_grad_entries<T>(A->row_ptr, A->col_idx, aval, p->m, p->nnzA, p->P, B->row_ptr,
+                           B->col_idx, bval, p->n, C->row_ptr, C->col_idx, dc, dA, W, s);
+  if (want_b) {
+    if (W) {
+      launch_grad_b_sum<T>(p->tptr, p->tpos, p->P, B->row_ptr, p->k, W, dB, s);
+      p->al.put(W, s);
+    } else {
+      launch_grad_b<T>(p->tptr, p->trow, p->tpos, aval, B->row_ptr, B->col_idx, p->k,
+                       C->row_ptr, C->col_idx, dc, dB, s);
+    }
+  }
+  return SPGEMM_OK;
+}
+
+}  // namespace
+
 extern "C" int spgemm_backward(spgemm_plan plan, const spgemm_csr *A, const spgemm_csr *B,
                                const spgemm_csr *C, void *dA_val, void *dB_val, void *stream) {
   if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
@@ -852,44 +913,9 @@ extern "C" int spgemm_backward(spgemm_plan plan, const spgemm_csr *A, const spge
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   p->stream = s;
   stage_begin(p, SPGEMM_T_BACKWARD, s);
-  if (dA_val && p->nnzA > 0) {
-    if (p->dtype == SPGEMM_F64)
-      launch_grad_a<double>(A->row_ptr, A->col_idx, p->m, B->row_ptr, B->col_idx,
-                            static_cast<const double *>(B->val), C->row_ptr, C->col_idx,
-                            static_cast<const double *>(C->val), static_cast<double *>(dA_val), s);
-    else
-      launch_grad_a<float>(A->row_ptr, A->col_idx, p->m, B->row_ptr, B->col_idx,
-                           static_cast<const float *>(B->val), C->row_ptr, C->col_idx,
-                           static_cast<const float *>(C->val), static_cast<float *>(dA_val), s);
-  }
-  if (dB_val && p->nnzB > 0) {
-    if (!p->bws) {
-      Layout L;
-      const size_t oc = L.add<int32_t>(p->k);
-      const size_t ot = L.add<int64_t>(p->k + 1);
-      const size_t orr = L.add<int32_t>(p->nnzA);
-      const size_t op = L.add<int32_t>(p->nnzA);
-      const size_t opa = L.add<int64_t>(scan_part_len(std::max<int64_t>(p->k, 1)));
-      p->bws = p->al.get(L.bytes(), s);
-      if (!p->bws) return fail(SPGEMM_ENOMEM, "backward scratch allocation failed");
-      p->tcnt = at<int32_t>(p->bws, oc);
-      p->tptr = at<int64_t>(p->bws, ot);
-      p->trow = at<int32_t>(p->bws, orr);
-      p->tpos = at<int32_t>(p->bws, op);
-      p->tpart = at<int64_t>(p->bws, opa);
-      p->info.bytes_scratch += static_cast<int64_t>(L.bytes());
-      launch_transpose_pattern(A->row_ptr, A->col_idx, p->m, p->k, p->nnzA, p->tcnt, p->tptr,
-                               p->trow, p->tpos, p->tpart, s);
-    }
-    if (p->dtype == SPGEMM_F64)
-      launch_grad_b<double>(p->tptr, p->trow, p->tpos, static_cast<const double *>(A->val),
-                            B->row_ptr, B->col_idx, p->k, C->row_ptr, C->col_idx,
-                            static_cast<const double *>(C->val), static_cast<double *>(dB_val), s);
-    else
-      launch_grad_b<float>(p->tptr, p->trow, p->tpos, static_cast<const float *>(A->val),
-                           B->row_ptr, B->col_idx, p->k, C->row_ptr, C->col_idx,
-                           static_cast<const float *>(C->val), static_cast<float *>(dB_val), s);
-  }
+  rc = p->dtype == SPGEMM_F64 ? backward_t<double>(p, A, B, C, dA_val, dB_val, s)
+                              : backward_t<float>(p, A, B, C, dA_val, dB_val, s);
+  if (rc != SPGEMM_OK) return rc;
   stage_end(p, SPGEMM_T_BACKWARD, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward");

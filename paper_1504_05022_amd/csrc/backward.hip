@@ -2,10 +2,12 @@
 //   dA_ij = sum over stored b_jk of dC_ik * b_jk       ((dC B^T) on S(A))
 //   dB_jk = sum over stored a_ij of a_ij * dC_ik       ((A^T dC) on S(B))
 // Every (i, k) reached lies in S(C) because S(C) is the structural product.
-// Both are gathers (no floating-point atomics): one wavefront per row of A
-// for dA, one per row of B for dB, the latter through A's transposed
-// pattern (rows of each column in ascending order).  Each sum runs in the
-// same order as the definition (ascending k, ascending i), from +0.0.
+// Both are gathers (no floating-point atomics).  dA, and the products
+// a_ij dC_ik of dB, come from an entry-parallel pass over A; dB then adds
+// those products per b_jk over A's transposed pattern (rows of each column in
+// ascending order).  Without room for the products, dB is gathered per row
+// of B with binary searches in C.  Each sum runs in the order of the
+// definition (ascending k, ascending i), from +0.0.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -20,28 +22,6 @@ DEVI int32_t find_col(const int32_t *col, int32_t lo, int32_t hi, int32_t c) {
       hi = mid;
   }
   return lo;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_grad_a(const int32_t *arp, const int32_t *acol,
-                                                int64_t m, const int32_t *brp,
-                                                const int32_t *bcol, const T *bval,
-                                                const int32_t *crp, const int32_t *ccol,
-                                                const T *dc, T *dA) {
-  const int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE;
-  if (i >= m) return;
-  const int32_t c0 = crp[i], c1 = crp[i + 1];
-  for (int32_t e = arp[i] + lane(); e < arp[i + 1]; e += WAVE) {
-    const int32_t j = acol[e];
-    T s = T(0);
-    int32_t lo = c0;
-    for (int32_t q = brp[j]; q < brp[j + 1]; ++q) {
-      const int32_t pc = find_col(ccol, lo, c1, bcol[q]);
-      s = s + dc[pc] * bval[q];
-      lo = pc + 1;  // columns of b_j* ascend
-    }
-    dA[e] = s;
-  }
 }
 
 template <typename T>
@@ -64,6 +44,148 @@ __global__ __launch_bounds__(256) void k_grad_b(const int64_t *tptr, const int32
     dB[q] = s;
   }
 }
+
+// ---------------------------------------------------------------------------
+// Entry-parallel form.  One wavefront per chunk of BW_CH consecutive entries
+// of A (rows found by a binary search on A's row pointers, so rows of any
+// length are spread evenly).  For every entry e = (i, j) and every stored
+// b_jk, y = dC_ik is looked up -- in a dense LDS copy of the row's dC when C
+// has few columns, else by a binary search in c_i* -- and
+//   dA_e += y * b_jk                  (ascending k, as in the definition)
+//   W[P_e + q] = a_ij * y             (q = position of b_jk in b_j*)
+// where P_e is the product offset of entry e from stage 1.  W holds every
+// product a_ij dC_ik of the dB sums; k_grad_b_sum adds them per b_jk over
+// A's transposed pattern (ascending i).  Sums, products and their order are
+// those of the definition (and of k_grad_b).
+constexpr int BW_CH = 1024;
+constexpr int BW_NT = 256;
+constexpr int BW_MAP_BYTES = 16384;  // dense dC row per wavefront
+
+template <typename T> constexpr int bw_map_cols() { return BW_MAP_BYTES / static_cast<int>(sizeof(T)); }
+
+template <typename T, bool DENSE>
+__global__ __launch_bounds__(BW_NT) void k_grad_entries(
+    const int32_t *arp, const int32_t *acol, const T *aval, int64_t m, int64_t nnz,
+    const int64_t *P, const int32_t *brp, const int32_t *bcol, const T *bval, const int32_t *crp,
+    const int32_t *ccol, const T *dc, T *dA, T *W) {
+  constexpr int NWV = BW_NT / WAVE;
+  constexpr int MAPC = DENSE ? bw_map_cols<T>() : 1;
+  __shared__ T map[NWV * MAPC];
+  const int w = threadIdx.x / WAVE;
+  const int ln = lane();
+  const int64_t e0 = (static_cast<int64_t>(blockIdx.x) * NWV + w) * BW_CH;
+  if (e0 >= nnz) return;  // uniform across the wavefront; no work-group barriers here
+  const int64_t e1 = e0 + BW_CH < nnz ? e0 + BW_CH : nnz;
+  T *mp = map + w * MAPC;
+  if (DENSE) {
+    for (int x = ln; x < MAPC; x += WAVE) mp[x] = T(0);
+    wave_sync();
+  }
+  int64_t lo = 0, hi = m;  // the row holding e0: last i with arp[i] <= e0
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (arp[mid] <= e0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  int64_t i = lo;
+  int64_t e = e0;
+  while (e < e1) {
+    while (arp[i + 1] <= e) ++i;  // skip empty rows
+    const int64_t re = arp[i + 1] < e1 ? static_cast<int64_t>(arp[i + 1]) : e1;
+    const int32_t c0 = crp[i], c1 = crp[i + 1];
+    if (DENSE) {
+      for (int32_t x = c0 + ln; x < c1; x += WAVE) mp[ccol[x]] = dc[x];
+      wave_sync();
+    }
+    for (int64_t ee = e + ln; ee < re; ee += WAVE) {
+      const int32_t j = acol[ee];
+      const T av = aval[ee];
+      const int32_t q0 = brp[j], q1 = brp[j + 1];
+      T *wp = W ? W + (P[ee] - q0) : nullptr;
+      T s = T(0);
+      int32_t from = c0;
+      for (int32_t q = q0; q < q1; ++q) {
+        const int32_t k = bcol[q];
+        T y;
+        if (DENSE) {
+          y = mp[k];
+        } else {
+          const int32_t pc = find_col(ccol, from, c1, k);
+          y = dc[pc];
+          from = pc + 1;  // columns of b_j* ascend
+        }
+        s = s + y * bval[q];
+        if (wp) wp[q] = av * y;
+      }
+      if (dA) dA[ee] = s;
+    }
+    if (DENSE) {
+      wave_sync();
+      for (int32_t x = c0 + ln; x < c1; x += WAVE) mp[ccol[x]] = T(0);
+      wave_sync();
+    }
+    e = re;
+  }
+}
+
+// dB_jk = sum over A's column j (ascending i) of the products a_ij dC_ik in W.
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_b_sum(const int64_t *tptr, const int32_t *tpos,
+                                                    const int64_t *P, const int32_t *brp,
+                                                    int64_t kb, const T *W, T *dB) {
+  const int64_t j = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE;
+  if (j >= kb) return;
+  const int64_t t0 = tptr[j], t1 = tptr[j + 1];
+  const int32_t q0 = brp[j], q1 = brp[j + 1];
+  for (int32_t q = q0 + lane(); q < q1; q += WAVE) {
+    T s = T(0);
+    for (int64_t d = t0; d < t1; ++d) s = s + W[P[tpos[d]] + (q - q0)];
+    dB[q] = s;
+  }
+}
+
+template <typename T>
+void launch_grad_entries(const int32_t *arp, const int32_t *acol, const T *aval, int64_t m,
+                         int64_t nnz, const int64_t *P, const int32_t *brp, const int32_t *bcol,
+                         const T *bval, int64_t n, const int32_t *crp, const int32_t *ccol,
+                         const T *dc, T *dA, T *W, hipStream_t s) {
+  if (nnz <= 0) return;
+  const int64_t waves = (nnz + BW_CH - 1) / BW_CH;
+  const int64_t grid = (waves + BW_NT / WAVE - 1) / (BW_NT / WAVE);
+  if (n <= bw_map_cols<T>())
+    hipLaunchKernelGGL((k_grad_entries<T, true>), dim3(grid), dim3(BW_NT), 0, s, arp, acol, aval,
+                       m, nnz, P, brp, bcol, bval, crp, ccol, dc, dA, W);
+  else
+    hipLaunchKernelGGL((k_grad_entries<T, false>), dim3(grid), dim3(BW_NT), 0, s, arp, acol,
+                       aval, m, nnz, P, brp, bcol, bval, crp, ccol, dc, dA, W);
+}
+
+template <typename T>
+void launch_grad_b_sum(const int64_t *tptr, const int32_t *tpos, const int64_t *P,
+                       const int32_t *brp, int64_t kb, const T *W, T *dB, hipStream_t s) {
+  if (kb <= 0) return;
+  hipLaunchKernelGGL((k_grad_b_sum<T>), dim3((kb * WAVE + 255) / 256), dim3(256), 0, s, tptr,
+                     tpos, P, brp, kb, W, dB);
+}
+
+template void launch_grad_entries<float>(const int32_t *, const int32_t *, const float *, int64_t,
+                                         int64_t, const int64_t *, const int32_t *,
+                                         const int32_t *, const float *, int64_t,
+                                         const int32_t *, const int32_t *, const float *, float *,
+                                         float *, hipStream_t);
+template void launch_grad_entries<double>(const int32_t *, const int32_t *, const double *,
+                                          int64_t, int64_t, const int64_t *, const int32_t *,
+                                          const int32_t *, const double *, int64_t,
+                                          const int32_t *, const int32_t *, const double *,
+                                          double *, double *, hipStream_t);
+template void launch_grad_b_sum<float>(const int64_t *, const int32_t *, const int64_t *,
+                                       const int32_t *, int64_t, const float *, float *,
+                                       hipStream_t);
+template void launch_grad_b_sum<double>(const int64_t *, const int32_t *, const int64_t *,
+                                        const int32_t *, int64_t, const double *, double *,
+                                        hipStream_t);
 
 // Column counts of A.
 __global__ void k_col_count(const int32_t *acol, int64_t nnz, int32_t *cnt) {
@@ -121,15 +243,6 @@ void launch_transpose_pattern(const int32_t *arp, const int32_t *acol, int64_t m
 }
 
 template <typename T>
-void launch_grad_a(const int32_t *arp, const int32_t *acol, int64_t m, const int32_t *brp,
-                   const int32_t *bcol, const T *bval, const int32_t *crp, const int32_t *ccol,
-                   const T *dc, T *dA, hipStream_t s) {
-  if (m <= 0) return;
-  hipLaunchKernelGGL((k_grad_a<T>), dim3((m * WAVE + 255) / 256), dim3(256), 0, s, arp, acol, m,
-                     brp, bcol, bval, crp, ccol, dc, dA);
-}
-
-template <typename T>
 void launch_grad_b(const int64_t *tptr, const int32_t *trow, const int32_t *tpos, const T *aval,
                    const int32_t *brp, const int32_t *bcol, int64_t kb, const int32_t *crp,
                    const int32_t *ccol, const T *dc, T *dB, hipStream_t s) {
@@ -138,12 +251,6 @@ void launch_grad_b(const int64_t *tptr, const int32_t *trow, const int32_t *tpos
                      tpos, aval, brp, bcol, kb, crp, ccol, dc, dB);
 }
 
-template void launch_grad_a<float>(const int32_t *, const int32_t *, int64_t, const int32_t *,
-                                   const int32_t *, const float *, const int32_t *,
-                                   const int32_t *, const float *, float *, hipStream_t);
-template void launch_grad_a<double>(const int32_t *, const int32_t *, int64_t, const int32_t *,
-                                    const int32_t *, const double *, const int32_t *,
-                                    const int32_t *, const double *, double *, hipStream_t);
 template void launch_grad_b<float>(const int64_t *, const int32_t *, const int32_t *,
                                    const float *, const int32_t *, const int32_t *, int64_t,
                                    const int32_t *, const int32_t *, const float *, float *,

@@ -280,8 +280,9 @@ template <typename T> struct LongArgs {
 
 // Long-row table, work items and piece map (three launches).
 void launch_long_table(const int32_t *binlist, int64_t off, int64_t nlong, const int64_t *u,
-                       int64_t ncols, LongParams lp, LongRow *lrows, LongItem *items,
-                       LongState *state, Seq *partials, int32_t *piece_lrow, int64_t *tmp,
+                       int64_t ncols, LongParams lp, LongRow *lrows, int64_t nitems,
+                       LongItem *items, LongState *state, Seq *partials, int64_t npieces,
+                       int32_t *piece_lrow, const int32_t *arp, const int64_t *P, int64_t *tmp,
                        hipStream_t s);
 void launch_cstate_init(LongState *state, int64_t n, hipStream_t s);
 int combine_maxs();
@@ -304,8 +305,6 @@ template <typename T>
 void launch_combine_wave(const LongArgs<T> &a, int64_t npieces, hipStream_t s);
 template <typename T>
 void launch_combine_oneshot(const LongArgs<T> &a, int64_t npieces, hipStream_t s);
-void launch_item_entry(const int32_t *arp, const int64_t *P, LongItem *items, int64_t n,
-                       hipStream_t s);
 template <typename T>
 int launch_combine(const LongArgs<T> &a, int64_t npieces, hipStream_t s);
 int long_l1cap_default(int dtype_bytes);
@@ -339,10 +338,16 @@ void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 void launch_transpose_pattern(const int32_t *arp, const int32_t *acol, int64_t m, int64_t k,
                               int64_t nnz, int32_t *cnt, int64_t *tptr, int32_t *trow,
                               int32_t *tpos, int64_t *part, hipStream_t s);
+// Entry-parallel gradient: dA (nullable) and the products W (nullable,
+// sum(u) entries) of the dB sums; then dB from W over A's transposed pattern.
 template <typename T>
-void launch_grad_a(const int32_t *arp, const int32_t *acol, int64_t m, const int32_t *brp,
-                   const int32_t *bcol, const T *bval, const int32_t *crp, const int32_t *ccol,
-                   const T *dc, T *dA, hipStream_t s);
+void launch_grad_entries(const int32_t *arp, const int32_t *acol, const T *aval, int64_t m,
+                         int64_t nnz, const int64_t *P, const int32_t *brp, const int32_t *bcol,
+                         const T *bval, int64_t n, const int32_t *crp, const int32_t *ccol,
+                         const T *dc, T *dA, T *W, hipStream_t s);
+template <typename T>
+void launch_grad_b_sum(const int64_t *tptr, const int32_t *tpos, const int64_t *P,
+                       const int32_t *brp, int64_t kb, const T *W, T *dB, hipStream_t s);
 template <typename T>
 void launch_grad_b(const int64_t *tptr, const int32_t *trow, const int32_t *tpos, const T *aval,
                    const int32_t *brp, const int32_t *bcol, int64_t kb, const int32_t *crp,

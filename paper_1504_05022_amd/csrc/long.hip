@@ -1915,30 +1915,6 @@ __global__ __launch_bounds__(WAVE_NT) void k_combine_w(LongArgs<T> a, int64_t np
   wave_piece<T, WAVE_K, Key, MAXS>(a, static_cast<int32_t>(id), s_a[w], s_b[w]);
 }
 
-// Entry of A's row that contains the first product of every item.
-__global__ void k_item_entry(const int32_t *arp, const int64_t *P, LongItem *items, int64_t n) {
-  const int64_t x = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (x >= n) return;
-  LongItem it = items[x];
-  const int32_t e0 = arp[it.row], e1 = arp[it.row + 1];
-  const int64_t pbase = P[e0];
-  int32_t lo = e0, hi = e1;
-  while (hi - lo > 1) {
-    const int32_t mid = (lo + hi) >> 1;
-    if (P[mid] - pbase <= it.p0)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  items[x].e_first = lo;
-}
-
-void launch_item_entry(const int32_t *arp, const int64_t *P, LongItem *items, int64_t n,
-                       hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_item_entry, dim3((n + 255) / 256), dim3(256), 0, s, arp, P, items, n);
-}
-
 // ------------------------------------------------------------ long table
 
 int64_t long_table_tmp_len(int64_t nlong) { return 4 * ((nlong + 255) / 256 + 1); }
@@ -2002,9 +1978,7 @@ __global__ void k_lt_scan(int64_t *tmp, int64_t nb) {
 __global__ __launch_bounds__(256) void k_lt_write(const int32_t *binlist, int64_t off,
                                                   int64_t nlong, const int64_t *u, int64_t ncols,
                                                   LongParams lp, const int64_t *tmp,
-                                                  LongRow *lrows, LongItem *items,
-                                                  LongState *state, Seq *partials,
-                                                  int32_t *piece_lrow) {
+                                                  LongRow *lrows) {
   __shared__ int64_t sm[256 / WAVE + 1];
   const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   LongRow lr;
@@ -2020,37 +1994,84 @@ __global__ __launch_bounds__(256) void k_lt_write(const int32_t *binlist, int64_
   lr.pbase = u0;
   lr.sbase = s0;
   lrows[t] = lr;
-  for (int32_t s = 0; s < lr.nseg; ++s) {
-    LongItem it;
-    it.row = lr.row;
-    it.lrow = static_cast<int32_t>(t);
-    it.p0 = static_cast<int64_t>(s) * lr.segp;
-    it.p1 = it.p0 + lr.segp < lr.u ? it.p0 + lr.segp : lr.u;
-    items[i0 + s] = it;
-    LongState st;
-    st.pos = it.p0;
-    st.gcnt = 0;
-    st.gcap = 0;
-    st.gcol = nullptr;
-    st.gval = nullptr;
-    st.scap = 0;
-    st.scol = nullptr;
-    st.sval = nullptr;
-    st.status = 0;
-    st.pad = 0;
-    state[i0 + s] = st;
-    Seq q;
-    q.col = nullptr;
-    q.val = nullptr;
-    q.cnt = 0;
-    partials[i0 + s] = q;
+}
+
+// Work items (one thread each): product range, first entry of A's row that
+// reaches it, an empty checkpoint and an empty partial.
+__global__ __launch_bounds__(256) void k_lt_items(const LongRow *lrows, int64_t nlong,
+                                                  int64_t nitems, const int32_t *arp,
+                                                  const int64_t *P, LongItem *items,
+                                                  LongState *state, Seq *partials) {
+  const int64_t x = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (x >= nitems) return;
+  int64_t lo = 0, hi = nlong;  // the row whose items include x
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (lrows[mid].item0 <= x)
+      lo = mid;
+    else
+      hi = mid;
   }
-  for (int32_t q = 0; q < lr.npiece; ++q) piece_lrow[p0 + q] = static_cast<int32_t>(t);
+  const LongRow lr = lrows[lo];
+  LongItem it;
+  it.row = lr.row;
+  it.lrow = static_cast<int32_t>(lo);
+  it.p0 = (x - lr.item0) * lr.segp;
+  it.p1 = it.p0 + lr.segp < lr.u ? it.p0 + lr.segp : lr.u;
+  {
+    const int32_t e0 = arp[lr.row], e1 = arp[lr.row + 1];
+    const int64_t pbase = P[e0];
+    int32_t a = e0, b = e1;  // last entry whose products start at or before p0
+    while (b - a > 1) {
+      const int32_t mid = (a + b) >> 1;
+      if (P[mid] - pbase <= it.p0)
+        a = mid;
+      else
+        b = mid;
+    }
+    it.e_first = a;
+  }
+  it.pad = 0;
+  items[x] = it;
+  LongState st;
+  st.pos = it.p0;
+  st.gcnt = 0;
+  st.gcap = 0;
+  st.gcol = nullptr;
+  st.gval = nullptr;
+  st.scap = 0;
+  st.scol = nullptr;
+  st.sval = nullptr;
+  st.status = 0;
+  st.pad = 0;
+  state[x] = st;
+  Seq q;
+  q.col = nullptr;
+  q.val = nullptr;
+  q.cnt = 0;
+  partials[x] = q;
+}
+
+// Row of every output piece (one thread each).
+__global__ __launch_bounds__(256) void k_lt_pieces(const LongRow *lrows, int64_t nlong,
+                                                   int64_t npieces, int32_t *piece_lrow) {
+  const int64_t x = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (x >= npieces) return;
+  int64_t lo = 0, hi = nlong;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (lrows[mid].piece0 <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  piece_lrow[x] = static_cast<int32_t>(lo);
 }
 
 void launch_long_table(const int32_t *binlist, int64_t off, int64_t nlong, const int64_t *u,
-                       int64_t ncols, LongParams lp, LongRow *lrows, LongItem *items,
-                       LongState *state, Seq *partials, int32_t *piece_lrow, int64_t *tmp,
+                       int64_t ncols, LongParams lp, LongRow *lrows, int64_t nitems,
+                       LongItem *items, LongState *state, Seq *partials, int64_t npieces,
+                       int32_t *piece_lrow, const int32_t *arp, const int64_t *P, int64_t *tmp,
                        hipStream_t s) {
   if (nlong <= 0) return;
   const int64_t nb = (nlong + 255) / 256;
@@ -2058,7 +2079,13 @@ void launch_long_table(const int32_t *binlist, int64_t off, int64_t nlong, const
                      tmp);
   hipLaunchKernelGGL(k_lt_scan, dim3(1), dim3(64), 0, s, tmp, nb);
   hipLaunchKernelGGL(k_lt_write, dim3(nb), dim3(256), 0, s, binlist, off, nlong, u, ncols, lp,
-                     tmp, lrows, items, state, partials, piece_lrow);
+                     tmp, lrows);
+  if (nitems > 0)
+    hipLaunchKernelGGL(k_lt_items, dim3((nitems + 255) / 256), dim3(256), 0, s, lrows, nlong,
+                       nitems, arp, P, items, state, partials);
+  if (npieces > 0)
+    hipLaunchKernelGGL(k_lt_pieces, dim3((npieces + 255) / 256), dim3(256), 0, s, lrows, nlong,
+                       npieces, piece_lrow);
 }
 
 // Checkpoints of the combine pieces: start of the stream, empty G.

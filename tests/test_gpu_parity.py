@@ -249,10 +249,12 @@ def test_errors():
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_backward_matches_oracle(dtype):
+@pytest.mark.parametrize("ncols", [256, 9000])
+def test_backward_matches_oracle(dtype, ncols):
+    """Few columns: dC rows held densely on chip; many: binary searches in C."""
     import torch
     from paper_1504_05022_amd import CsrMatrix, Plan
-    A, B = S.config5(n=3000, ncols=256)
+    A, B = S.config5(n=3000, ncols=ncols)
     A, B = A.astype(dtype), B.astype(dtype)
     dA, dB = CsrMatrix.from_host(A), CsrMatrix.from_host(B)
     plan = Plan(dA, dB)
