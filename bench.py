@@ -32,7 +32,7 @@ WORKLOAD = ("irregular C=A*A, A 200000x200000 CSR, power-law row degrees "
 LONG_MIN = 512
 WAVE_TILE = 1024
 MAX_SEGS = 512
-RANGE_TARGET = WAVE_TILE // 2
+RANGE_TARGET = WAVE_TILE // 4
 MIN_SHIFT, MAX_SHIFT = 4, 30
 
 
@@ -81,15 +81,17 @@ def ranges_to_index(starts, lens):
 
 
 def wave_kernel_bytes(A, B, crp, cci, s):
-    """Algorithmic bytes of the two one-wavefront long-row kernels.
+    """Algorithmic bytes of the first passes of the two one-wavefront
+    long-row kernels.
 
-    Segment kernel, per segment of at most WAVE_TILE products: its A entries
-    (P, column, value, B's row pointer: 16 + s bytes each), the gathered B
-    entries (4 + s each) and what it writes (the row's result for a one-
-    segment row, the segment's products plus its range starts otherwise).
-    Range kernel, per column range of a split row: the range starts and
-    partial records of every segment (32 bytes each), its entries (4 + s
-    each, only if it holds at most WAVE_TILE of them) and its result."""
+    Segment kernel (first pass: the 512-product segments of rows longer
+    than 1024 products), per segment: its A entries (P, column, value, B's
+    row pointer: 16 + s bytes each), the gathered B entries (4 + s each) and
+    the segment's products plus its range starts, which it writes.
+    Range kernel (its first pass, 512-entry wavefront sorts), per column
+    range of a split row: the range starts and partial records of every
+    segment (32 bytes each), its entries (4 + s each, only if it holds at
+    most 512 of them; larger ranges go on to the next pass) and its result."""
     arp = A.row_ptr.astype(np.int64)
     brp = B.row_ptr.astype(np.int64)
     deg = np.diff(arp)
@@ -108,11 +110,10 @@ def wave_kernel_bytes(A, B, crp, cci, s):
         starts = np.cumsum(lens) - lens
         ends = starts + lens
         if ui <= WAVE_TILE:
-            seg_bytes += (e1 - e0) * (16 + s) + ui * (4 + s) + int(cnnz[i]) * (4 + s) + 128
-            continue
-        segp = max(WAVE_TILE, -(-ui // MAX_SEGS))
-        if segp > WAVE_TILE:
-            continue  # not a one-wavefront row
+            continue  # one-item row: the second (1024-product) pass
+        segp = max(WAVE_TILE // 2, -(-ui // MAX_SEGS))
+        if segp > WAVE_TILE // 2:
+            continue  # segments too long for the first pass
         nseg = -(-ui // segp)
         wdt = -(-(n * RANGE_TARGET) // ui)
         shift = min(max(int(math.ceil(math.log2(max(wdt, 1)))), MIN_SHIFT), MAX_SHIFT)
@@ -125,7 +126,7 @@ def wave_kernel_bytes(A, B, crp, cci, s):
         cols = B.col_idx[ranges_to_index(brp[js], bdeg[js])]
         E = np.bincount(cols >> shift, minlength=npiece)
         r = np.bincount(cci[int(crp[i]):int(crp[i + 1])] >> shift, minlength=npiece)
-        small = E <= WAVE_TILE
+        small = E <= WAVE_TILE // 2  # the first (512-entry) wavefront pass
         rng_bytes += npiece * nseg * 32 + int((E[small] + r[small]).sum()) * (4 + s) + npiece * 64
     return seg_bytes, rng_bytes
 
@@ -286,9 +287,9 @@ def main():
 
     # dominant kernel: the longer of the two one-wavefront long-row kernels
     seg_bytes, rng_bytes = wave_kernel_bytes(A, A, crp, cci, s)
-    cand = [("k_long_w (long-row segments, one wavefront each)", seg_bytes,
+    cand = [("k_long_w (512-product segments of split rows, one wavefront each)", seg_bytes,
              stages["long_wave"]),
-            ("k_combine_w (column ranges of split rows, one wavefront each)", rng_bytes,
+            ("k_combine_w (column ranges of split rows, 512-entry wavefront pass)", rng_bytes,
              stages["combine_wave"])]
     name, kbytes, kms = max(cand, key=lambda c: c[2])
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0

@@ -100,7 +100,8 @@ typedef struct {
                            kernel, 0 = automatic                              */
   int64_t seg;          /* max products per long-row work item (rows with
                            more are split across work-groups); 0 = automatic
-                           (1024, one wavefront), < 0 = never split          */
+                           (rows up to 1024 stay whole, longer ones are cut
+                           into 512), < 0 = never split                      */
   int64_t pool_entries; /* initial long-row pool size in entries, 0 = auto   */
   int32_t validate;     /* nonzero: check the input CSR arrays on the device  */
   int32_t timing;       /* nonzero: record per-stage times into spgemm_info   */

@@ -327,10 +327,13 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   p->l1cap = o.l1_cap ? o.l1_cap : long_l1cap_default(dtype_bytes(p->dtype));
   // default segment: one tile of the one-pass kernel, and never more than
   // the level-1 sequence can take without spilling
-  // default segments and combine ranges fit one wavefront (kWaveTile)
-  p->lp.segp = o.seg < 0 ? -1 : (o.seg > 0 ? o.seg : kWaveTile);
+  // defaults: a row of up to kWaveTile products is one item; longer rows are
+  // cut into segments of kWaveTile / 2 (one wavefront each, at twice the
+  // occupancy of a full tile), and combine ranges aim at kWaveTile / 4
+  p->lp.segp = o.seg < 0 ? -1 : (o.seg > 0 ? o.seg : kWaveTile / 2);
+  p->lp.single = o.seg != 0 ? 0 : kWaveTile;
   p->lp.maxs = combine_maxs();
-  p->lp.cb = kWaveTile / 2;
+  p->lp.cb = kWaveTile / 4;
   p->lp.minw_shift = 4;
   p->lp.maxw_shift = 30;
   const int64_t nh = static_cast<int64_t>(NBINS) * p->nwaves;
@@ -508,7 +511,9 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   const size_t ogl = L.add<unsigned int>(nitems);
   const size_t ogl2 = L.add<unsigned int>(npieces);
   const size_t ol1 = L.add<unsigned int>(nitems);
+  const size_t olw = L.add<unsigned int>(nitems);
   const size_t ol2 = L.add<unsigned int>(npieces);
+  const size_t ol3 = L.add<unsigned int>(npieces);
   p->cws_bytes = L.bytes();
   p->cws = p->al.get(p->cws_bytes, s);
   if (!p->cws) return fail(SPGEMM_ENOMEM, "C~ allocation failed");
@@ -537,7 +542,9 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   unsigned int *glist = at<unsigned int>(p->cws, ogl);
   unsigned int *glist2 = at<unsigned int>(p->cws, ogl2);
   unsigned int *list1 = at<unsigned int>(p->cws, ol1);
+  unsigned int *listw = at<unsigned int>(p->cws, olw);
   unsigned int *list2 = at<unsigned int>(p->cws, ol2);
+  unsigned int *list3 = at<unsigned int>(p->cws, ol3);
 
   EscArgs<T> ea;
   ea.arp = A->row_ptr;
@@ -605,7 +612,9 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   la.glist = glist;
   la.glist2 = glist2;
   la.list1 = list1;
+  la.listw = listw;
   la.list2 = list2;
+  la.list3 = list3;
   la.ncols = p->n;
   const bool spill_expected = S.spill_bound > 0 || p->opt.pool_entries > 0;
   auto new_pool = [&](int64_t entries, unsigned long long used) -> int {
@@ -632,7 +641,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   if (nlong > 0) {
     pool_entries = p->opt.pool_entries
                        ? p->opt.pool_entries
-                       : S.pool_single + S.sum_r_multi + 3 * S.spill_bound + 65536;
+                       : S.pool_single + 3 * S.spill_bound + 65536;
     if ((rc = new_pool(pool_entries, 0)) != SPGEMM_OK) return rc;
     launch_long_table(p->binlist, S.bin_off[LONG_BIN], nlong, p->u, p->n, p->lp, lrows, nitems,
                       items, states, partials, npieces, piece_lrow, A->row_ptr, p->P, lt_tmp, s);
@@ -644,6 +653,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     stage_begin(p, SPGEMM_T_LONG_WAVE, s);
     launch_long_wave<T>(la, nitems, s);
     stage_end(p, SPGEMM_T_LONG_WAVE, s);
+    launch_long_wave_large<T>(la, nitems, s);
     launch_long_oneshot<T>(la, nitems, s);
     if (launch_long<T>(la, nitems, p->l1cap, s))
       return fail(SPGEMM_EINVAL, "no long-row kernel for this l1_cap");
@@ -675,6 +685,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
       stage_begin(p, SPGEMM_T_COMBINE_WAVE, s);
       launch_combine_wave<T>(la, npieces, s);
       stage_end(p, SPGEMM_T_COMBINE_WAVE, s);
+      launch_combine_wave_large<T>(la, npieces, s);
       launch_combine_oneshot<T>(la, npieces, s);
       launch_combine<T>(la, npieces, s);
       stage_end(p, SPGEMM_T_COMBINE, s);
@@ -711,6 +722,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
         la.fail_list2 = f2;
         if (S.n_split > 0) {  // some row was split
           launch_combine_wave<T>(la, npieces, s);
+          launch_combine_wave_large<T>(la, npieces, s);
           launch_combine_oneshot<T>(la, npieces, s);
           launch_combine<T>(la, npieces, s);
         }

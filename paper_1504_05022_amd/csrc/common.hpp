@@ -22,6 +22,15 @@ DEVI void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A pointer known to address global memory (one read back from memory or
+// LDS is generic, and generic loads are also counted with the LDS
+// operations, which makes later LDS reads wait for them).
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <typename T> DEVI const GLOBAL_AS T *as_global(const T *p) {
+  return (const GLOBAL_AS T *)p;
+}
+template <typename T> DEVI GLOBAL_AS T *as_global_mut(T *p) { return (GLOBAL_AS T *)p; }
+
 // ---------------------------------------------------------------- shuffles
 
 DEVI uint32_t shfl_xor_u32(uint32_t v, int m) {
@@ -33,6 +42,14 @@ DEVI uint64_t shfl_xor_u64(uint64_t v, int m) {
 template <typename K> DEVI K shfl_xor_key(K v, int m);
 template <> DEVI uint32_t shfl_xor_key<uint32_t>(uint32_t v, int m) { return shfl_xor_u32(v, m); }
 template <> DEVI uint64_t shfl_xor_key<uint64_t>(uint64_t v, int m) { return shfl_xor_u64(v, m); }
+
+template <typename K> DEVI K shfl_key(K v, int src);
+template <> DEVI uint32_t shfl_key<uint32_t>(uint32_t v, int src) {
+  return static_cast<uint32_t>(__shfl(static_cast<int>(v), src, WAVE));
+}
+template <> DEVI uint64_t shfl_key<uint64_t>(uint64_t v, int src) {
+  return static_cast<uint64_t>(__shfl(static_cast<long long>(v), src, WAVE));
+}
 
 template <typename K> DEVI K shfl_up_key(K v, int d);
 template <> DEVI uint32_t shfl_up_key<uint32_t>(uint32_t v, int d) {

@@ -1,41 +1,135 @@
 // Stage 4 of the framework ("arranging data", Section 3.1): after the row
 // sizes of C have been scanned into C's row pointers, copy every row from
-// the temporary matrix C~ into C.  Short rows are copied by one wavefront
-// each (in row order, so consecutive waves write consecutive parts of C);
-// long rows are copied piece by piece by whole work-groups, so that the
-// longest rows do not serialise on one wavefront.
+// the temporary matrix C~ into C.  A wavefront takes 32 consecutive short
+// rows and streams all their entries at once, so the copy is coalesced and
+// no wavefront waits on one row's metadata; long rows are copied piece by
+// piece by whole work-groups.
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace spg {
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_compact_rows(CompactArgs<T> a, int64_t m) {
-  const int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE;
-  if (i >= m) return;
-  const int64_t o = a.rowoff[i];
-  if (lane() == 0) {
-    a.c_rp[i] = static_cast<int32_t>(o);
-    if (i == m - 1) a.c_rp[m] = static_cast<int32_t>(a.rowoff[m]);
-  }
-  if (a.u[i] > a.long_min) return;  // copied by k_compact_pieces
-  const int64_t n = a.rowoff[i + 1] - o;
-  const int64_t src = a.cto[i];
-  for (int64_t x = lane(); x < n; x += WAVE) {
-    a.c_col[o + x] = a.ct_col[src + x];
-    a.c_val[o + x] = a.ct_val[src + x];
+constexpr int CP_NT = 256;
+constexpr int CP_ROWS = 32;    // short rows per wavefront
+constexpr int CP_BATCH = 4;    // passes whose loads are issued before their stores
+
+// LDS table of the sources of one wavefront.
+template <int R> struct CopyTable {
+  int64_t pre[R];   // first stream index of every source
+  int64_t dst[R];   // destination index of its first entry
+  int64_t col[R];   // source column / value pointers
+  int64_t val[R];
+};
+
+// Copy up to R sources held one per lane (n entries from scol/sval to dst)
+// as one stream: every pass moves 64 consecutive entries of their
+// concatenation, one per lane, so loads and stores are coalesced along every
+// source.  The source of an entry is found by a binary search in the
+// wavefront's table, so passes are independent: the loads of the next
+// CP_BATCH passes are issued before the stores of the current ones (the
+// memory counter that a load waits on also counts earlier stores).
+template <typename T, int R> struct StreamBatch {
+  int32_t c[CP_BATCH];
+  T v[CP_BATCH];
+  int64_t d[CP_BATCH];
+};
+
+// Loads of one batch, without branches (a pass beyond the stream rereads its
+// last entry and is not stored), so that the compiler can keep them in
+// flight across the stores of the previous batch.
+template <typename T, int R>
+DEVI void stream_load(const CopyTable<R> &tb, int64_t x0, int64_t tot, StreamBatch<T, R> &sb) {
+#pragma unroll
+  for (int b = 0; b < CP_BATCH; ++b) {
+    const int64_t xr = x0 + b * WAVE + lane();
+    const int64_t x = xr < tot ? xr : tot - 1;
+    int lo = 0;  // last source starting at or before x (it is not empty)
+#pragma unroll
+    for (int step = R / 2; step >= 1; step >>= 1)
+      lo = tb.pre[lo + step] <= x ? lo + step : lo;
+    const int64_t off = x - tb.pre[lo];
+    sb.c[b] = as_global(reinterpret_cast<const int32_t *>(tb.col[lo]))[off];
+    sb.v[b] = as_global(reinterpret_cast<const T *>(tb.val[lo]))[off];
+    sb.d[b] = xr < tot ? tb.dst[lo] + off : -1;
   }
 }
 
+template <typename T, int R>
+DEVI void stream_store(const StreamBatch<T, R> &sb, int32_t *dcol, T *dval) {
+#pragma unroll
+  for (int b = 0; b < CP_BATCH; ++b) {
+    if (sb.d[b] >= 0) {
+      dcol[sb.d[b]] = sb.c[b];
+      dval[sb.d[b]] = sb.v[b];
+    }
+  }
+}
+
+template <typename T, int R>
+DEVI void wave_stream_copy(int64_t n, const int32_t *scol, const T *sval, int64_t dst,
+                           int32_t *dcol, T *dval, CopyTable<R> &tb) {
+  static_assert((R & (R - 1)) == 0 && R <= WAVE, "R must be a power of two up to 64");
+  const int ln = lane();
+  const int64_t incl = group_incl_sum<WAVE>(n);
+  const int64_t tot = __shfl(static_cast<long long>(incl), WAVE - 1, WAVE);
+  if (ln < R) {
+    tb.pre[ln] = incl - n;
+    tb.dst[ln] = dst;
+    tb.col[ln] = reinterpret_cast<int64_t>(scol);
+    tb.val[ln] = reinterpret_cast<int64_t>(sval);
+  }
+  wave_sync();
+  if (tot <= 0) return;
+  constexpr int64_t STEP = static_cast<int64_t>(CP_BATCH) * WAVE;
+  // two register batches in turn: the loads of one are in flight while the
+  // other is stored
+  StreamBatch<T, R> ba, bb;
+  stream_load<T, R>(tb, 0, tot, ba);
+  for (int64_t x0 = 0; x0 < tot; x0 += 2 * STEP) {
+    if (x0 + STEP < tot) stream_load<T, R>(tb, x0 + STEP, tot, bb);
+    stream_store<T, R>(ba, dcol, dval);
+    if (x0 + STEP >= tot) break;
+    if (x0 + 2 * STEP < tot) stream_load<T, R>(tb, x0 + 2 * STEP, tot, ba);
+    stream_store<T, R>(bb, dcol, dval);
+  }
+}
+
+// Row pointers of C, and the short rows (u <= long_min) copied from C~:
+// CP_ROWS consecutive rows per wavefront.
 template <typename T>
-__global__ __launch_bounds__(256) void k_compact_pieces(CompactArgs<T> a) {
+__global__ __launch_bounds__(CP_NT) void k_compact_rows(CompactArgs<T> a, int64_t m) {
+  __shared__ CopyTable<CP_ROWS> tabs[CP_NT / WAVE];
+  const int64_t w = (static_cast<int64_t>(blockIdx.x) * CP_NT + threadIdx.x) / WAVE;
+  const int64_t r0 = w * CP_ROWS;
+  if (r0 >= m) return;  // uniform across the wavefront
+  const int64_t r = r0 + lane();
+  int64_t n = 0, src = 0, o = 0;
+  if (lane() < CP_ROWS && r < m) {
+    o = a.rowoff[r];
+    const int64_t o1 = a.rowoff[r + 1];
+    a.c_rp[r] = static_cast<int32_t>(o);
+    if (r == m - 1) a.c_rp[m] = static_cast<int32_t>(o1);
+    if (a.u[r] <= a.long_min) {
+      n = o1 - o;
+      src = a.cto[r];
+    }
+  }
+  wave_stream_copy<T, CP_ROWS>(n, a.ct_col + src, a.ct_val + src, o, a.c_col, a.c_val,
+                               tabs[threadIdx.x / WAVE]);
+}
+
+// Long rows, piece by piece: one work-group per piece (pieces hold a few
+// hundred to a few thousand entries).
+template <typename T>
+__global__ __launch_bounds__(CP_NT) void k_compact_pieces(CompactArgs<T> a) {
   const Piece pc = a.pieces[blockIdx.x];
   if (pc.cnt <= 0) return;
   const LongRow lr = a.lrows[pc.lrow];
   const int64_t dst = a.rowoff[lr.row] + a.pscan[blockIdx.x] - a.pscan[lr.piece0];
-  const T *sv = reinterpret_cast<const T *>(pc.val);
-  for (int64_t x = threadIdx.x; x < pc.cnt; x += blockDim.x) {
-    a.c_col[dst + x] = pc.col[x];
+  const GLOBAL_AS int32_t *sc = as_global(pc.col);
+  const GLOBAL_AS T *sv = as_global(reinterpret_cast<const T *>(pc.val));
+  for (int64_t x = threadIdx.x; x < pc.cnt; x += CP_NT) {
+    a.c_col[dst + x] = sc[x];
     a.c_val[dst + x] = sv[x];
   }
 }
@@ -43,10 +137,11 @@ __global__ __launch_bounds__(256) void k_compact_pieces(CompactArgs<T> a) {
 template <typename T>
 void launch_compact(const CompactArgs<T> &a, int64_t m, int64_t npieces, hipStream_t s) {
   if (m <= 0) return;
-  const int64_t nb = (m * WAVE + 255) / 256;
-  hipLaunchKernelGGL((k_compact_rows<T>), dim3(nb), dim3(256), 0, s, a, m);
+  const int64_t rwaves = (m + CP_ROWS - 1) / CP_ROWS;
+  hipLaunchKernelGGL((k_compact_rows<T>), dim3((rwaves * WAVE + CP_NT - 1) / CP_NT), dim3(CP_NT),
+                     0, s, a, m);
   if (npieces > 0)
-    hipLaunchKernelGGL((k_compact_pieces<T>), dim3(npieces), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_compact_pieces<T>), dim3(npieces), dim3(CP_NT), 0, s, a);
 }
 
 template void launch_compact<float>(const CompactArgs<float> &, int64_t, int64_t, hipStream_t);

@@ -44,27 +44,41 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
   // lane are G apart, so lanes touch consecutive words (no bank conflicts)
   constexpr int LOGK = Log2<K>::v;
   auto ix = [](int l) { return (l & (K - 1)) * G + (l >> LOGK); };
+  // every array is in global memory (the batched kernel reads these
+  // pointers from memory, which would otherwise make them generic)
+  const GLOBAL_AS int64_t *gu = as_global(a.u);
+  const GLOBAL_AS int32_t *garp = as_global(a.arp);
+  const GLOBAL_AS int64_t *gP = as_global(a.P);
+  const GLOBAL_AS int32_t *gacol = as_global(a.acol);
+  const GLOBAL_AS T *gaval = as_global(a.aval);
+  const GLOBAL_AS int32_t *gbrp = as_global(a.brp);
+  const GLOBAL_AS int32_t *gbcol = as_global(a.bcol);
+  const GLOBAL_AS T *gbval = as_global(a.bval);
+  const GLOBAL_AS int64_t *gcto = as_global(a.cto);
+  GLOBAL_AS int32_t *gct_col = as_global_mut(a.ct_col);
+  GLOBAL_AS T *gct_val = as_global_mut(a.ct_val);
+  GLOBAL_AS int64_t *grownnz = as_global_mut(a.rownnz);
   const int64_t r = base + grp;
-  const int32_t i = r < nrows ? rows[r] : 0;
+  const int32_t i = r < nrows ? as_global(rows)[r] : 0;
   // rows of this launch have u <= U by binning; the check keeps every LDS
   // and global index in range even if that were violated
-  const bool act = r < nrows && a.u[i] <= U;
-  const int u = act ? static_cast<int>(a.u[i]) : 0;
-  const int32_t e0 = act ? a.arp[i] : 0;
-  const int32_t e1 = act ? a.arp[i + 1] : 0;
-  const int64_t pbase = act ? a.P[e0] : 0;
+  const bool act = r < nrows && gu[i] <= U;
+  const int u = act ? static_cast<int>(gu[i]) : 0;
+  const int32_t e0 = act ? garp[i] : 0;
+  const int32_t e1 = act ? garp[i + 1] : 0;
+  const int64_t pbase = act ? gP[e0] : 0;
 
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) rs[kk * G + pos] = -1;
   wave_sync();
   // run starts: entry e of row i contributes products [P[e]-P[e0], P[e+1]-P[e0])
   for (int32_t e = e0 + pos; e < e1; e += G) {
-    const int64_t s0 = a.P[e] - pbase;
-    const int64_t w = a.P[e + 1] - a.P[e];
+    const int64_t s0 = gP[e] - pbase;
+    const int64_t w = gP[e + 1] - gP[e];
     if (w > 0) {
-      const int32_t j = a.acol[e];
-      rs[ix(static_cast<int>(s0))] = a.brp[j];
-      ra[ix(static_cast<int>(s0))] = a.aval[e];
+      const int32_t j = gacol[e];
+      rs[ix(static_cast<int>(s0))] = gbrp[j];
+      ra[ix(static_cast<int>(s0))] = gaval[e];
     }
   }
   wave_sync();
@@ -118,8 +132,8 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
     if (l < u) {
       const int32_t bidx = gb[l];
       const T av = ga[l];
-      const int32_t c = a.bcol[bidx];
-      const T bv = a.bval[bidx];
+      const int32_t c = gbcol[bidx];
+      const T bv = gbval[bidx];
       prod[kk] = av * bv;
       key[kk] = (static_cast<Key>(c) << LOGU) | static_cast<Key>(l);
     }
@@ -153,7 +167,7 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
   const int incl_h = group_incl_sum<G>(nh);
   const int total = group_last<G>(incl_h);
   if (act) {
-    int64_t o = a.cto[i] + (incl_h - nh);
+    int64_t o = gcto[i] + (incl_h - nh);
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) {
       if (hmask & (1u << kk)) {
@@ -166,12 +180,12 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
           if ((k2 >> LOGU) != c) break;
           v = v + pv[static_cast<int>(k2 & (U - 1))];
         }
-        a.ct_col[o] = static_cast<int32_t>(c);
-        a.ct_val[o] = v;
+        gct_col[o] = static_cast<int32_t>(c);
+        gct_val[o] = v;
         ++o;
       }
     }
-    if (pos == 0) a.rownnz[i] = total;
+    if (pos == 0) grownnz[i] = total;
   }
   wave_sync();
 }

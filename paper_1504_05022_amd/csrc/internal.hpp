@@ -62,6 +62,7 @@ struct Summary {
 //    ranges of all partials in segment order into one output piece.
 struct LongParams {
   int64_t segp;      // products per segment; < 0: never split
+  int64_t single;    // rows with at most this many products stay one item
   int32_t maxs;      // at most this many segments per row (segp grows)
   int32_t cb;        // target entries per combine range
   int32_t minw_shift;
@@ -77,7 +78,7 @@ __host__ __device__ inline int32_t ceil_log2_i64(int64_t x) {
 __host__ __device__ inline void long_row_plan(int64_t u, int64_t n, const LongParams &lp,
                                               int64_t &segp, int32_t &nseg, int32_t &shift,
                                               int32_t &npiece) {
-  if (lp.segp < 0 || u <= lp.segp) {
+  if (lp.segp < 0 || u <= lp.segp || u <= lp.single) {
     segp = u > 0 ? u : 1;
     nseg = 1;
     shift = 0;
@@ -131,7 +132,9 @@ struct LongCounters {
   unsigned int glong;  // items for the general kernel
   unsigned int gcomb;  // pieces for the general combine kernel
   unsigned int l1;     // items for the one-tile work-group kernel
-  unsigned int l2;     // pieces for the one-tile work-group combine kernel
+  unsigned int l2;     // pieces for the second wavefront combine pass
+  unsigned int l3;     // pieces for the one-tile work-group combine kernel
+  unsigned int lw;     // items for the second wavefront pass
 };
 
 // Sorted, duplicate-free sequence in device memory.
@@ -274,7 +277,9 @@ template <typename T> struct LongArgs {
   unsigned int *glist;    // items left to the general (multi-tile) kernel
   unsigned int *glist2;   // pieces left to the general combine kernel
   unsigned int *list1;    // items too large for one wavefront
-  unsigned int *list2;    // pieces too large for one wavefront
+  unsigned int *listw;    // items too large for the first wavefront pass
+  unsigned int *list2;    // pieces too large for the first wavefront pass
+  unsigned int *list3;    // pieces too large for one wavefront
   int64_t ncols;
 };
 
@@ -302,7 +307,11 @@ template <typename T> void launch_long_oneshot(const LongArgs<T> &a, int64_t nit
 constexpr int kWaveTile = 1024;
 template <typename T> void launch_long_wave(const LongArgs<T> &a, int64_t nitems, hipStream_t s);
 template <typename T>
+void launch_long_wave_large(const LongArgs<T> &a, int64_t nitems, hipStream_t s);
+template <typename T>
 void launch_combine_wave(const LongArgs<T> &a, int64_t npieces, hipStream_t s);
+template <typename T>
+void launch_combine_wave_large(const LongArgs<T> &a, int64_t npieces, hipStream_t s);
 template <typename T>
 void launch_combine_oneshot(const LongArgs<T> &a, int64_t npieces, hipStream_t s);
 template <typename T>

@@ -1514,21 +1514,21 @@ DEVI void combine1_piece(LongArgs<T> &a, const int32_t pid, unsigned char *s_a, 
                                         sg_val, s_a, s_b, sh);
 }
 
-// One piece per work-group, or (list2 set) the pieces listed by the
-// wavefront kernel, in a grid-stride loop.
+// One piece per work-group, or (list3 set) the pieces listed by the
+// wavefront kernels, in a grid-stride loop.
 template <typename T, int NT, int TILE, typename Key, int MAXS>
 __global__ __launch_bounds__(NT) void k_combine1(LongArgs<T> a) {
   __shared__ __align__(16) unsigned char s_a[Combine1Lds<NT, TILE, Key, MAXS>::bytes_a];
   __shared__ __align__(16) T s_b[TILE];
   __shared__ MergeShared<T> sh;
-  if (a.list2 == nullptr) {
+  if (a.list3 == nullptr) {
     combine1_piece<T, NT, TILE, Key, MAXS>(a, static_cast<int32_t>(blockIdx.x), s_a, s_b, sh);
     return;
   }
-  const unsigned int n = a.cnt->l2;
+  const unsigned int n = a.cnt->l3;
   for (unsigned int w = blockIdx.x; w < n; w += gridDim.x) {
     __syncthreads();
-    combine1_piece<T, NT, TILE, Key, MAXS>(a, static_cast<int32_t>(a.list2[w]), s_a, s_b, sh);
+    combine1_piece<T, NT, TILE, Key, MAXS>(a, static_cast<int32_t>(a.list3[w]), s_a, s_b, sh);
   }
 }
 
@@ -1644,7 +1644,28 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
     const int l = kk * WAVE + pos;
     if (l < tn) pv[l] = prod[kk];
   }
-  group_bitonic_sort<WAVE, K, Key>(key);
+  // a tile inside one sorted run of B (about a fifth of the tiles of
+  // power-law rows) is already in order: it only changes lanes
+  bool ordered = true;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = kk * WAVE + pos;
+    const Key right = shfl_key<Key>(key[kk], (pos + 1) & (WAVE - 1));
+    const Key wrap = shfl_key<Key>(key[kk + 1 < K ? kk + 1 : kk], 0);
+    const Key next = pos < WAVE - 1 ? right : wrap;
+    if (l + 1 < tn && !(key[kk] < next)) ordered = false;
+  }
+  if (__all(ordered)) {
+    wave_sync();  // gb is dead
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) sk[wix<K>(kk * WAVE + pos)] = key[kk];
+    wave_sync();
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) key[kk] = sk[kk * WAVE + pos];
+  } else {
+    group_bitonic_sort<WAVE, K, Key>(key);
+  }
+  wave_sync();
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) sk[kk * WAVE + pos] = key[kk];
   const Key pk = shfl_up_key<Key>(key[K - 1], 1);
@@ -1737,32 +1758,45 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
   }
 }
 
-template <typename T, typename Key>
-__global__ __launch_bounds__(WAVE_NT) void k_long_w(LongArgs<T> a, int64_t nitems) {
+// Every item (in_list == nullptr), or the listed ones in a grid-stride
+// loop; items above 64 K products go to out_list.
+template <typename T, typename Key, int K>
+__global__ __launch_bounds__(WAVE_NT) void k_long_w(LongArgs<T> a, int64_t nitems,
+                                                    const unsigned int *in_list,
+                                                    const unsigned int *in_cnt,
+                                                    unsigned int *out_list,
+                                                    unsigned int *out_cnt) {
   constexpr int NWV = WAVE_NT / WAVE;
+  constexpr int U = WAVE * K;
   constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
-  __shared__ __align__(16) unsigned char s_a[NWV][kWaveTile * KB];
-  __shared__ __align__(16) T s_b[NWV][kWaveTile];
+  __shared__ __align__(16) unsigned char s_a[NWV][U * KB];
+  __shared__ __align__(16) T s_b[NWV][U];
   const int w = threadIdx.x / WAVE;
-  const int64_t id = static_cast<int64_t>(blockIdx.x) * NWV + w;
-  if (id >= nitems) return;  // uniform across the wavefront; no work-group barriers here
-  const LongItem item = a.items[id];
-  if (item.p1 - item.p0 > kWaveTile) {
-    if (lane() == 0) a.list1[atomicAdd(&a.cnt->l1, 1u)] = static_cast<unsigned int>(id);
-    return;
+  const int64_t id0 = static_cast<int64_t>(blockIdx.x) * NWV + w;
+  const int64_t n = in_list ? static_cast<int64_t>(*in_cnt) : nitems;
+  const int64_t stride = in_list ? static_cast<int64_t>(gridDim.x) * NWV : n;
+  // uniform across the wavefront; no work-group barriers here
+  for (int64_t x = id0; x < n; x += stride) {
+    const int32_t id = static_cast<int32_t>(in_list ? in_list[x] : x);
+    const LongItem item = a.items[id];
+    if (item.p1 - item.p0 > U) {
+      if (lane() == 0) out_list[atomicAdd(out_cnt, 1u)] = static_cast<unsigned int>(id);
+      continue;
+    }
+    wave_item<T, K, Key>(a, id, item, s_a[w], s_b[w]);
   }
-  wave_item<T, WAVE_K, Key>(a, static_cast<int32_t>(id), item, s_a[w], s_b[w]);
 }
 
 // One piece of a split row by one wavefront: the piece's range of every
 // partial, concatenated in segment order, sorted on (column, stream index),
 // folded in that order.  Larger pieces are listed for the work-group kernel.
 template <typename T, int K, typename Key, int MAXS>
-DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T *lds_b) {
+DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T *lds_b,
+                     unsigned int *olist, unsigned int *ocnt) {
   constexpr int U = WAVE * K;
   constexpr int LOGU = Log2<U>::v;
   constexpr Key KMAX = KeyMax<Key>::v;
-  static_assert(2 * MAXS * 4 <= U * 4, "segment table exceeds the key buffer");
+  static_assert(MAXS <= U, "segment table exceeds the tile buffers");
   const int pos = lane();
   const int32_t lri = a.piece_lrow[pid];
   const LongRow lr = a.lrows[lri];
@@ -1771,10 +1805,11 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
   const int32_t c0 = b << lr.shift;
   const int32_t nseg = lr.nseg;
   const int32_t *ptab = a.split + lr.sbase;
-  // segment table (aliases the key buffer): first stream index of every
-  // segment, and the partial-buffer index of stream index 0 for it
+  // segment table (in the tile buffers, dead before they are used): first
+  // stream index of every segment, and the partial-buffer index of stream
+  // index 0 for it
   int32_t *toff = reinterpret_cast<int32_t *>(lds_a);
-  int32_t *tbase = toff + MAXS;
+  int32_t *tbase = reinterpret_cast<int32_t *>(lds_b);
   int64_t carry = 0, obase = 0;
   for (int32_t s0 = 0; s0 < nseg; s0 += WAVE) {
     const int32_t s = s0 + pos;
@@ -1798,7 +1833,7 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
   }
   const int64_t E = carry;
   if (E > U) {
-    if (pos == 0) a.list2[atomicAdd(&a.cnt->l2, 1u)] = static_cast<unsigned int>(pid);
+    if (pos == 0) olist[atomicAdd(ocnt, 1u)] = static_cast<unsigned int>(pid);
     return;
   }
   wave_sync();
@@ -1903,16 +1938,30 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
   }
 }
 
-template <typename T, typename Key, int MAXS>
-__global__ __launch_bounds__(WAVE_NT) void k_combine_w(LongArgs<T> a, int64_t npieces) {
+// Every piece (in_list == nullptr), or the listed ones in a grid-stride
+// loop; pieces above 64 K entries go to out_list.
+template <typename T, typename Key, int MAXS, int K>
+__global__ __launch_bounds__(WAVE_NT) void k_combine_w(LongArgs<T> a, int64_t npieces,
+                                                       const unsigned int *in_list,
+                                                       const unsigned int *in_cnt,
+                                                       unsigned int *out_list,
+                                                       unsigned int *out_cnt) {
   constexpr int NWV = WAVE_NT / WAVE;
+  constexpr int U = WAVE * K;
   constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
-  __shared__ __align__(16) unsigned char s_a[NWV][kWaveTile * KB];
-  __shared__ __align__(16) T s_b[NWV][kWaveTile];
+  __shared__ __align__(16) unsigned char s_a[NWV][U * KB];
+  __shared__ __align__(16) T s_b[NWV][U];
   const int w = threadIdx.x / WAVE;
   const int64_t id = static_cast<int64_t>(blockIdx.x) * NWV + w;
-  if (id >= npieces) return;
-  wave_piece<T, WAVE_K, Key, MAXS>(a, static_cast<int32_t>(id), s_a[w], s_b[w]);
+  if (in_list == nullptr) {
+    if (id >= npieces) return;  // uniform across the wavefront; no work-group barriers here
+    wave_piece<T, K, Key, MAXS>(a, static_cast<int32_t>(id), s_a[w], s_b[w], out_list, out_cnt);
+    return;
+  }
+  const int64_t n = *in_cnt;
+  for (int64_t x = id; x < n; x += static_cast<int64_t>(gridDim.x) * NWV)
+    wave_piece<T, K, Key, MAXS>(a, static_cast<int32_t>(in_list[x]), s_a[w], s_b[w], out_list,
+                                out_cnt);
 }
 
 // ------------------------------------------------------------ long table
@@ -2166,7 +2215,7 @@ template <typename T> void launch_long_oneshot(const LongArgs<T> &a, int64_t nit
 template <typename T>
 void launch_combine_oneshot(const LongArgs<T> &a, int64_t npieces, hipStream_t s) {
   if (npieces <= 0) return;
-  const int64_t grid = a.list2 ? std::min<int64_t>(npieces, LIST_GRID) : npieces;
+  const int64_t grid = a.list3 ? std::min<int64_t>(npieces, LIST_GRID) : npieces;
   if ((static_cast<uint64_t>(a.ncols) << Log2<kOneShot>::v) <= 0xffffffffull)
     hipLaunchKernelGGL((k_combine1<T, ONESHOT_NT, kOneShot, uint32_t, COMBINE_MAXS>),
                        dim3(grid), dim3(ONESHOT_NT), 0, s, a);
@@ -2175,25 +2224,59 @@ void launch_combine_oneshot(const LongArgs<T> &a, int64_t npieces, hipStream_t s
                        dim3(grid), dim3(ONESHOT_NT), 0, s, a);
 }
 
+template <typename T, int K>
+static void long_wave_k(const LongArgs<T> &a, int64_t nitems, int64_t grid,
+                        const unsigned int *in_list, const unsigned int *in_cnt,
+                        unsigned int *out_list, unsigned int *out_cnt, hipStream_t s) {
+  if ((static_cast<uint64_t>(a.ncols) << Log2<WAVE * K>::v) <= 0xffffffffull)
+    hipLaunchKernelGGL((k_long_w<T, uint32_t, K>), dim3(grid), dim3(WAVE_NT), 0, s, a, nitems,
+                       in_list, in_cnt, out_list, out_cnt);
+  else
+    hipLaunchKernelGGL((k_long_w<T, uint64_t, K>), dim3(grid), dim3(WAVE_NT), 0, s, a, nitems,
+                       in_list, in_cnt, out_list, out_cnt);
+}
+
+// Items of up to 512 products (every segment of a split row) in one pass,
+// larger ones (one-item rows up to 1024) in a second, then the lists.
 template <typename T> void launch_long_wave(const LongArgs<T> &a, int64_t nitems, hipStream_t s) {
   if (nitems <= 0) return;
   const int64_t grid = (nitems + WAVE_NT / WAVE - 1) / (WAVE_NT / WAVE);
-  if ((static_cast<uint64_t>(a.ncols) << Log2<kWaveTile>::v) <= 0xffffffffull)
-    hipLaunchKernelGGL((k_long_w<T, uint32_t>), dim3(grid), dim3(WAVE_NT), 0, s, a, nitems);
+  long_wave_k<T, WAVE_K / 2>(a, nitems, grid, nullptr, nullptr, a.listw, &a.cnt->lw, s);
+}
+
+template <typename T>
+void launch_long_wave_large(const LongArgs<T> &a, int64_t nitems, hipStream_t s) {
+  if (nitems <= 0) return;
+  const int64_t grid =
+      std::min<int64_t>((nitems + WAVE_NT / WAVE - 1) / (WAVE_NT / WAVE), LIST_GRID);
+  long_wave_k<T, WAVE_K>(a, nitems, grid, a.listw, &a.cnt->lw, a.list1, &a.cnt->l1, s);
+}
+
+template <typename T, int K>
+static void combine_wave_k(const LongArgs<T> &a, int64_t npieces, int64_t grid,
+                           const unsigned int *in_list, const unsigned int *in_cnt,
+                           unsigned int *out_list, unsigned int *out_cnt, hipStream_t s) {
+  if ((static_cast<uint64_t>(a.ncols) << Log2<WAVE * K>::v) <= 0xffffffffull)
+    hipLaunchKernelGGL((k_combine_w<T, uint32_t, COMBINE_MAXS, K>), dim3(grid), dim3(WAVE_NT), 0,
+                       s, a, npieces, in_list, in_cnt, out_list, out_cnt);
   else
-    hipLaunchKernelGGL((k_long_w<T, uint64_t>), dim3(grid), dim3(WAVE_NT), 0, s, a, nitems);
+    hipLaunchKernelGGL((k_combine_w<T, uint64_t, COMBINE_MAXS, K>), dim3(grid), dim3(WAVE_NT), 0,
+                       s, a, npieces, in_list, in_cnt, out_list, out_cnt);
 }
 
 template <typename T>
 void launch_combine_wave(const LongArgs<T> &a, int64_t npieces, hipStream_t s) {
   if (npieces <= 0) return;
   const int64_t grid = (npieces + WAVE_NT / WAVE - 1) / (WAVE_NT / WAVE);
-  if ((static_cast<uint64_t>(a.ncols) << Log2<kWaveTile>::v) <= 0xffffffffull)
-    hipLaunchKernelGGL((k_combine_w<T, uint32_t, COMBINE_MAXS>), dim3(grid), dim3(WAVE_NT), 0, s,
-                       a, npieces);
-  else
-    hipLaunchKernelGGL((k_combine_w<T, uint64_t, COMBINE_MAXS>), dim3(grid), dim3(WAVE_NT), 0, s,
-                       a, npieces);
+  combine_wave_k<T, WAVE_K / 2>(a, npieces, grid, nullptr, nullptr, a.list2, &a.cnt->l2, s);
+}
+
+template <typename T>
+void launch_combine_wave_large(const LongArgs<T> &a, int64_t npieces, hipStream_t s) {
+  if (npieces <= 0) return;
+  const int64_t grid =
+      std::min<int64_t>((npieces + WAVE_NT / WAVE - 1) / (WAVE_NT / WAVE), LIST_GRID);
+  combine_wave_k<T, WAVE_K>(a, npieces, grid, a.list2, &a.cnt->l2, a.list3, &a.cnt->l3, s);
 }
 
 template <typename T>
@@ -2237,7 +2320,11 @@ template void launch_combine_oneshot<float>(const LongArgs<float> &, int64_t, hi
 template void launch_combine_oneshot<double>(const LongArgs<double> &, int64_t, hipStream_t);
 template void launch_long_wave<float>(const LongArgs<float> &, int64_t, hipStream_t);
 template void launch_long_wave<double>(const LongArgs<double> &, int64_t, hipStream_t);
+template void launch_long_wave_large<float>(const LongArgs<float> &, int64_t, hipStream_t);
+template void launch_long_wave_large<double>(const LongArgs<double> &, int64_t, hipStream_t);
 template void launch_combine_wave<float>(const LongArgs<float> &, int64_t, hipStream_t);
 template void launch_combine_wave<double>(const LongArgs<double> &, int64_t, hipStream_t);
+template void launch_combine_wave_large<float>(const LongArgs<float> &, int64_t, hipStream_t);
+template void launch_combine_wave_large<double>(const LongArgs<double> &, int64_t, hipStream_t);
 
 }  // namespace spg
