@@ -31,6 +31,21 @@ template <typename T> DEVI const GLOBAL_AS T *as_global(const T *p) {
 }
 template <typename T> DEVI GLOBAL_AS T *as_global_mut(T *p) { return (GLOBAL_AS T *)p; }
 
+// Work-groups are dealt to the 8 XCDs (each with its own L2) in turn.  This
+// maps the hardware order to a logical one in which every XCD receives runs
+// of C consecutive logical ids (the runs themselves dealt in turn), so that
+// neighbouring work, which shares cache lines, stays in one L2 while uneven
+// work is still spread over all XCDs.  A bijection on [0, gridDim.x): the
+// last partial round of 8 C work-groups keeps the hardware order.
+constexpr int kNumXcd = 8;
+template <int C> DEVI int64_t xcd_block_id() {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t full = nb / (kNumXcd * C) * (kNumXcd * C);
+  if (b >= full) return b;
+  const int64_t x = b % kNumXcd, i = b / kNumXcd;
+  return (i / C) * (kNumXcd * C) + x * C + (i % C);
+}
+
 // ---------------------------------------------------------------- shuffles
 
 DEVI uint32_t shfl_xor_u32(uint32_t v, int m) {

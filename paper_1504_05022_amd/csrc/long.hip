@@ -1549,6 +1549,11 @@ constexpr int WAVE_K = kWaveTile / WAVE;
 // consecutive words).
 template <int K> DEVI int wix(int l) { return (l & (K - 1)) * WAVE + (l >> Log2<K>::v); }
 
+// Rank r of a sorted wavefront tile lives at r + r / 64: lane-blocked writes
+// (lane p, ranks p*K ..) and lane-striped reads (lane p, ranks k*64 + p)
+// are both free of LDS bank conflicts.  A tile needs U + U / 64 slots.
+DEVI int wpad(int r) { return r + (r >> 6); }
+
 template <typename T, int K, typename Key>
 DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
                     unsigned char *lds_a, T *lds_b) {
@@ -1658,16 +1663,17 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
   if (__all(ordered)) {
     wave_sync();  // gb is dead
 #pragma unroll
-    for (int kk = 0; kk < K; ++kk) sk[wix<K>(kk * WAVE + pos)] = key[kk];
+    for (int kk = 0; kk < K; ++kk) sk[wpad(kk * WAVE + pos)] = key[kk];
     wave_sync();
 #pragma unroll
-    for (int kk = 0; kk < K; ++kk) key[kk] = sk[kk * WAVE + pos];
+    for (int kk = 0; kk < K; ++kk) key[kk] = sk[wpad(pos * K + kk)];
   } else {
     group_bitonic_sort<WAVE, K, Key>(key);
   }
+  // sorted keys by rank (rank pos * K + kk is in key[kk])
   wave_sync();
 #pragma unroll
-  for (int kk = 0; kk < K; ++kk) sk[kk * WAVE + pos] = key[kk];
+  for (int kk = 0; kk < K; ++kk) sk[wpad(pos * K + kk)] = key[kk];
   const Key pk = shfl_up_key<Key>(key[K - 1], 1);
   wave_sync();
 
@@ -1680,19 +1686,24 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
     int32_t *ptab = a.split + lr.sbase;
     int32_t *dcol = a.pcol + lr.pbase + p0;
     T *dval = a.pval + lr.pbase + p0;
+    // rank r = kk * 64 + lane: consecutive lanes write consecutive entries
+    Key carry = 0;  // key of the rank before this pass's first
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) {
-      const int l = pos * K + kk;
-      if (l < tn) {
-        const int32_t c = static_cast<int32_t>(key[kk] >> LOGU);
-        dcol[l] = c;
-        dval[l] = pv[static_cast<int>(key[kk] & (U - 1))];
-        const Key before = kk > 0 ? key[kk - 1] : pk;
+      const int r = kk * WAVE + pos;
+      const Key kr = r < tn ? sk[wpad(r)] : KMAX;
+      Key before = shfl_up_key<Key>(kr, 1);
+      if (pos == 0) before = carry;
+      carry = shfl_key<Key>(kr, WAVE - 1);
+      if (r < tn) {
+        const int32_t c = static_cast<int32_t>(kr >> LOGU);
+        dcol[r] = c;
+        dval[r] = pv[static_cast<int>(kr & (U - 1))];
         const int32_t q = c >> shift;
-        const int32_t qp = l > 0 ? (static_cast<int32_t>(before >> LOGU) >> shift) : -1;
+        const int32_t qp = r > 0 ? (static_cast<int32_t>(before >> LOGU) >> shift) : -1;
         for (int32_t qq = qp + 1; qq <= q && qq < np; ++qq)
-          ptab[static_cast<int64_t>(qq) * nseg + s] = l;
-        if (l == tn - 1)
+          ptab[static_cast<int64_t>(qq) * nseg + s] = r;
+        if (r == tn - 1)
           for (int32_t qq = q + 1; qq <= np; ++qq) ptab[static_cast<int64_t>(qq) * nseg + s] = tn;
       }
     }
@@ -1734,7 +1745,7 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
       T v = T(0);
       v = v + pv[static_cast<int>(key[kk] & (U - 1))];
       for (int l2 = l + 1; l2 < tn; ++l2) {
-        const Key k2 = sk[wix<K>(l2)];
+        const Key k2 = sk[wpad(l2)];
         if ((k2 >> LOGU) != c) break;
         v = v + pv[static_cast<int>(k2 & (U - 1))];
       }
@@ -1769,10 +1780,10 @@ __global__ __launch_bounds__(WAVE_NT) void k_long_w(LongArgs<T> a, int64_t nitem
   constexpr int NWV = WAVE_NT / WAVE;
   constexpr int U = WAVE * K;
   constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
-  __shared__ __align__(16) unsigned char s_a[NWV][U * KB];
+  __shared__ __align__(16) unsigned char s_a[NWV][(U + U / WAVE) * KB];
   __shared__ __align__(16) T s_b[NWV][U];
   const int w = threadIdx.x / WAVE;
-  const int64_t id0 = static_cast<int64_t>(blockIdx.x) * NWV + w;
+  const int64_t id0 = xcd_block_id<16>() * NWV + w;
   const int64_t n = in_list ? static_cast<int64_t>(*in_cnt) : nitems;
   const int64_t stride = in_list ? static_cast<int64_t>(gridDim.x) * NWV : n;
   // uniform across the wavefront; no work-group barriers here

@@ -163,6 +163,33 @@ def test_long_row_splitting(seg):
     check(A2, A2, exact=False, seg=seg)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("seg", [0, 1024, 2048, 4096])
+def test_split_rows_are_exact(dtype, seg):
+    """Long rows cut into segments (512 products by default, or `seg`) and
+    column ranges that all fit one tile: phase 1 only orders each segment and
+    phase 2 folds every column in (segment, position) order, which is
+    Gustavson's order -- every value is the oracle's sequential sum."""
+    from paper_1504_05022_amd import CsrMatrix, Plan
+    import torch
+    A, B = S.crafted_rows([1500, 5000, 20000, 60000, 700, 3000], n=60000, dtype=dtype)
+    print("case: split rows exact,", dtype, "seg", seg, flush=True)
+    dA, dB = CsrMatrix.from_host(A), CsrMatrix.from_host(B)
+    plan = Plan(dA, dB, seg=seg)
+    C = plan.compute()
+    torch.cuda.synchronize()
+    assert plan.info.long_items > 6  # the rows were split
+    _, _, rp, ci, v = C.to_host()
+    plan.close()
+    if dtype == np.float32:
+        ref = oracle.spgemm(A.as_tuple(), B.as_tuple(), acc32=True)
+    else:
+        ref = oracle.spgemm(A.as_tuple(), B.as_tuple())
+    assert np.array_equal(rp.astype(np.int64), ref.row_ptr)
+    assert np.array_equal(ci, ref.col_idx)
+    assert np.array_equal(v.astype(np.float64), ref.val.astype(np.float64))
+
+
 def test_collision_heavy_rows_split():
     """Workload-5-like rows (u >> n): many segments whose partials overlap in
     almost every column."""
