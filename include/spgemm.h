@@ -105,6 +105,11 @@ typedef struct {
   int64_t pool_entries; /* initial long-row pool size in entries, 0 = auto   */
   int32_t validate;     /* nonzero: check the input CSR arrays on the device  */
   int32_t timing;       /* nonzero: record per-stage times into spgemm_info   */
+  int32_t timing_mask;  /* with timing: 0 times every stage, else only the
+                           stages whose bit (1 << SPGEMM_T_x) is set.  Every
+                           timed stage adds two event records to the stream,
+                           and spgemm_compute waits for the end of the last
+                           timed stage before it returns                     */
 } spgemm_options;
 
 #define SPGEMM_NBINS 38

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -197,8 +198,9 @@ struct spgemm_plan_s {
   spgemm_info info{};
   hipEvent_t ev[2 * SPGEMM_NSTAGES] = {};
   bool events = false;
+  int dev = 0;              // device the events belong to
+  uint32_t tmask = 0;       // stages to time
   uint32_t stage_mask = 0;  // stages recorded since the last read-back
-  std::vector<hipEvent_t> long_ev;
 };
 
 extern "C" {
@@ -237,6 +239,32 @@ const char *spgemm_last_error(void) { return g_last_error.c_str(); }
 
 namespace {
 
+// Timing events outlive plans: created once per device and reused, since
+// creating and destroying two dozen events per plan costs more host time
+// than the kernels of a small product take.
+std::mutex g_ev_mu;
+std::vector<std::pair<int, hipEvent_t>> g_ev_free;
+
+hipError_t take_event(int dev, hipEvent_t *e) {
+  {
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    for (size_t i = g_ev_free.size(); i-- > 0;) {
+      if (g_ev_free[i].first == dev) {
+        *e = g_ev_free[i].second;
+        g_ev_free.erase(g_ev_free.begin() + static_cast<std::ptrdiff_t>(i));
+        return hipSuccess;
+      }
+    }
+  }
+  return hipEventCreate(e);
+}
+
+void give_event(int dev, hipEvent_t e) {
+  if (!e) return;
+  std::lock_guard<std::mutex> lk(g_ev_mu);
+  g_ev_free.emplace_back(dev, e);
+}
+
 void release_compute(spgemm_plan p, hipStream_t s) {
   p->al.put(p->cws, s);
   p->cws = nullptr;
@@ -251,8 +279,7 @@ void destroy_plan(spgemm_plan p) {
   p->al.put(p->ws, p->stream);
   p->al.put(p->bws, p->stream);
   if (p->events)
-    for (auto &e : p->ev) (void)hipEventDestroy(e);
-  for (auto &e : p->long_ev) (void)hipEventDestroy(e);
+    for (auto &e : p->ev) give_event(p->dev, e);
   delete p;
 }
 
@@ -268,16 +295,19 @@ int check_options(const spgemm_options &o) {
       o.l1_cap != 7168)
     return fail(SPGEMM_EINVAL, "l1_cap must be 0, 2048, 3072, 5120 or 7168");
   if (o.pool_entries < 0) return fail(SPGEMM_EINVAL, "pool_entries must be >= 0");
+  if (o.timing_mask < 0 || o.timing_mask >= (1 << SPGEMM_NSTAGES))
+    return fail(SPGEMM_EINVAL, "timing_mask has bits beyond the stage count");
   return SPGEMM_OK;
 }
 
+bool timed(spgemm_plan p, int st) { return p->events && (p->tmask & (1u << st)); }
 void stage_begin(spgemm_plan p, int st, hipStream_t s) {
-  if (!p->events) return;
+  if (!timed(p, st)) return;
   (void)hipEventRecord(p->ev[2 * st], s);
   p->stage_mask |= 1u << st;
 }
 void stage_end(spgemm_plan p, int st, hipStream_t s) {
-  if (p->events) (void)hipEventRecord(p->ev[2 * st + 1], s);
+  if (timed(p, st)) (void)hipEventRecord(p->ev[2 * st + 1], s);
 }
 
 }  // namespace
@@ -325,8 +355,6 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   p->nwaves = (m + 63) / 64;  // one histogram column per 64-row wavefront
   p->nblocks = (m + 255) / 256;
   p->l1cap = o.l1_cap ? o.l1_cap : long_l1cap_default(dtype_bytes(p->dtype));
-  // default segment: one tile of the one-pass kernel, and never more than
-  // the level-1 sequence can take without spilling
   // defaults: a row of up to kWaveTile products is one item; longer rows are
   // cut into segments of kWaveTile / 2 (one wavefront each, at twice the
   // occupancy of a full tile), and combine ranges aim at kWaveTile / 4
@@ -379,8 +407,11 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   p->hstat = &p->hstat_store;
   p->hpool = &p->hpool_store;
   if (o.timing) {
+    (void)hipGetDevice(&p->dev);
+    p->tmask = o.timing_mask ? static_cast<uint32_t>(o.timing_mask)
+                             : (1u << SPGEMM_NSTAGES) - 1u;
     for (auto &e : p->ev) {
-      if (hipEventCreate(&e) != hipSuccess) {
+      if (take_event(p->dev, &e) != hipSuccess) {
         destroy_plan(p);
         return fail(SPGEMM_EHIP, "hipEventCreate failed");
       }
@@ -462,10 +493,8 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   for (int b = 0; b < NBINS; ++b) I.bin_count[b] = S.bin_off[b + 1] - S.bin_off[b];
   I.long_items = S.n_items;
   I.bytes_scratch = static_cast<int64_t>(p->ws_bytes);
-  if (p->events) {
-    (void)hipEventElapsedTime(&I.stage_ms[SPGEMM_T_UPPER], p->ev[0], p->ev[1]);
-    (void)hipEventElapsedTime(&I.stage_ms[SPGEMM_T_BIN], p->ev[2], p->ev[3]);
-  }
+  for (int st : {SPGEMM_T_UPPER, SPGEMM_T_BIN})
+    if (timed(p, st)) (void)hipEventElapsedTime(&I.stage_ms[st], p->ev[2 * st], p->ev[2 * st + 1]);
   if (info) *info = I;
   *plan = p;
   return SPGEMM_OK;
@@ -816,14 +845,16 @@ extern "C" int spgemm_compute(spgemm_plan plan, const spgemm_csr *A, const spgem
     return rc;
   }
   if (p->events) {
-    HIP_TRY(hipEventSynchronize(p->ev[2 * SPGEMM_T_COPY + 1]));
+    // waits only for the timed stages (the copy into C may still run)
     static const int kComputeStages[] = {SPGEMM_T_TINY,   SPGEMM_T_MEDIUM,    SPGEMM_T_LONG,
                                          SPGEMM_T_SCAN,   SPGEMM_T_COPY,      SPGEMM_T_LONG_WAVE,
                                          SPGEMM_T_COMBINE, SPGEMM_T_COMBINE_WAVE};
     for (int st : kComputeStages) {
       p->info.stage_ms[st] = 0.f;
-      if (p->stage_mask & (1u << st))
+      if (p->stage_mask & (1u << st)) {
+        HIP_TRY(hipEventSynchronize(p->ev[2 * st + 1]));
         (void)hipEventElapsedTime(&p->info.stage_ms[st], p->ev[2 * st], p->ev[2 * st + 1]);
+      }
     }
     p->stage_mask = 0;
     p->info.long_kernel_ms = p->info.stage_ms[SPGEMM_T_LONG];

@@ -41,6 +41,7 @@ def test_status_strings(lib):
     o = L.default_options()
     assert list(o.bin_edges) == [32, 64, 128, 256, 512]
     assert o.long_slot == 256
+    assert o.timing == 0 and o.timing_mask == 0
 
 
 def test_struct_layout_matches_c(tmp_path):

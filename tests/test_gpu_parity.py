@@ -214,7 +214,10 @@ def test_options_do_not_change_result():
     (rp0, ci0, v0), _ = check(A, A, seg=4096)
     (rp1, ci1, v1), _ = check(A, A, seg=4096, bin_edges=(16, 48, 100, 300, 700))
     (rp2, ci2, v2), _ = check(A, A, seg=4096, bin_edges=(8, 16, 32, 64, 128), l1_cap=7168)
-    for ci, v in ((ci1, v1), (ci2, v2)):
+    # stage timers (all, then two) do not change the result
+    (rp4, ci4, v4), _ = check(A, A, seg=4096, timing=1)
+    (rp5, ci5, v5), _ = check(A, A, seg=4096, timing=1, timing_mask=(1 << 8) | (1 << 10))
+    for ci, v in ((ci1, v1), (ci2, v2), (ci4, v4), (ci5, v5)):
         assert np.array_equal(ci, ci0) and np.array_equal(v, v0)
     # a smaller level-1 sequence spills more often: same structure, values
     # within tolerance (checked inside check())
@@ -272,6 +275,8 @@ def test_errors():
     # options out of range
     with pytest.raises(SpgemmError):
         Plan(dA, dA, bin_edges=(40, 64, 128, 256, 512))
+    with pytest.raises(SpgemmError):
+        Plan(dA, dA, timing=1, timing_mask=1 << 20)
     torch.cuda.synchronize()
 
 
