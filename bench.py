@@ -187,7 +187,8 @@ def memory_accounting(A, crp, info, s):
 
 def extensions(args, torch, S, L):
     """Batched (workload 4) and differentiable (workload 5) forms against the
-    plain path on the same GPU."""
+    plain path on the same GPU, and both orders of the multigrid Galerkin
+    products."""
     out = {}
     reps = 5
     # ---- batched: 512 banded problems, mixed binary32 / binary64
@@ -259,7 +260,59 @@ def extensions(args, torch, S, L):
             "backward_over_forward": round(bwms / fms, 3), "flops_forward": fl}
     except Exception as e:
         out["backward"] = {"error": repr(e)[:300]}
+    torch.cuda.empty_cache()
+    # ---- Galerkin products R*A*P of the multigrid experiment, both orders
+    try:
+        out["galerkin"] = galerkin_orders(torch, S, L, reps)
+    except Exception as e:
+        out["galerkin"] = {"error": repr(e)[:300]}
     return out
+
+
+def galerkin_orders(torch, S, L, reps):
+    """R*(A*P) against (R*A)*P for the 2D 5-/9-point (1024^2) and 3D
+    7-/27-point (101^3) stencils with unsmoothed 2^d aggregation, binary64:
+    time of both products (analysis and computation each), their flops, and
+    whether the two orders agree bit for bit (small-integer values: exact)."""
+    res = {}
+    for name in S.GALERKIN:
+        dim, points, g = S.GALERKIN[name]
+        A, P, R = S.galerkin(name)
+        dA, dP, dR = (L.CsrMatrix.from_host(x) for x in (A, P, R))
+        del A, P, R
+
+        def right():
+            AP, i1 = L.spgemm(dA, dP, return_info=True)
+            C, i2 = L.spgemm(dR, AP, return_info=True)
+            return C, int(i1.flops) + int(i2.flops)
+
+        def left():
+            RA, i1 = L.spgemm(dR, dA, return_info=True)
+            C, i2 = L.spgemm(RA, dP, return_info=True)
+            return C, int(i1.flops) + int(i2.flops)
+
+        row = {"grid": "%d^%d" % (g, dim), "n_fine": g ** dim}
+        outs = {}
+        for key, f in (("R(AP)", right), ("(RA)P", left)):
+            C, fl = f()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                f()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            outs[key] = C
+            row[key] = {"ms": round(ms, 3), "flops": fl, "gflops": round(fl / (ms * 1e-3) / 1e9, 2)}
+        c1, c2 = outs["R(AP)"], outs["(RA)P"]
+        row["nnz_coarse"] = int(c1.nnz)
+        row["orders_equal"] = bool(torch.equal(c1.row_ptr, c2.row_ptr)
+                                   and torch.equal(c1.col_idx, c2.col_idx)
+                                   and torch.equal(c1.val, c2.val))
+        row["faster"] = min(("R(AP)", "(RA)P"), key=lambda k: row[k]["ms"])
+        res[name] = row
+        del outs, c1, c2, dA, dP, dR
+        torch.cuda.empty_cache()
+    return res
 
 
 def main():

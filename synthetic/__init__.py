@@ -16,6 +16,12 @@ from .gen import (  # noqa: F401
     stencil27,
     aggregation_p,
     aggregation_r,
+    stencil,
+    aggregates,
+    aggregation_p_grid,
+    aggregation_r_grid,
+    GALERKIN,
+    galerkin,
     banded_csr,
     config1,
     config2,

@@ -10,7 +10,10 @@ CUSP AMG hierarchies, which are not available):
    U[-1, 1] in binary64; C = A*A.
 3. Galerkin product R*(A*P) of algebraic multigrid: A is the 27-point stencil
    on a 64^3 grid (diagonal 26, off-diagonals -1, truncated at the boundary),
-   P aggregates 2x2x2 blocks (entries 1.0), R = P^T, all binary64.
+   P aggregates 2x2x2 blocks (entries 1.0), R = P^T, all binary64.  The
+   multigrid experiment's other problems (2D 5- and 9-point stencils on
+   1024^2, 3D 7- and 27-point stencils on 101^3, both multiplication orders)
+   use the same construction (`galerkin`).
 4. 512 independent banded products A_i*B_i, n_i log-uniform in [1024, 65536],
    per-row degree uniform in {4..32}, columns in a band of width ceil(0.05 n)
    around the diagonal, binary64 for even i and binary32 for odd i,
@@ -26,6 +29,7 @@ per-matrix sub-stream key.
 """
 from __future__ import annotations
 
+import itertools
 import math
 from dataclasses import dataclass
 
@@ -241,6 +245,88 @@ def aggregation_r(g=64, dtype=np.float64) -> Csr:
     c.sort(axis=1)
     return Csr(nc, g ** 3, _row_ptr(np.full(nc, 8, dtype=np.int64)),
                c.reshape(-1).astype(np.int32), np.ones(nc * 8, dtype=dtype))
+
+
+def stencil(g, dim, points, dtype=np.float64) -> Csr:
+    """Constant-coefficient stencil on a grid of g points per side in `dim`
+    dimensions (fine index x + g*y, or x + g*(y + g*z)), truncated at the
+    boundary.  points = 2*dim + 1 couples each point to its axis neighbours
+    (2D 5-point, 3D 7-point); points = 3**dim to every point of its unit cube
+    (2D 9-point, 3D 27-point).  Off-diagonals are -1 and the diagonal is the
+    neighbour count (4, 6, 8 or 26), so interior rows sum to zero."""
+    if points not in (2 * dim + 1, 3 ** dim):
+        raise ValueError("points must be 2*dim+1 or 3**dim")
+    n = g ** dim
+    f = np.arange(n, dtype=np.int64)
+    coord = [(f // g ** k) % g for k in range(dim)]
+    nb = points - 1
+    rows, cols, vals = [], [], []
+    for off in itertools.product((-1, 0, 1), repeat=dim):
+        if points == 2 * dim + 1 and sum(abs(o) for o in off) > 1:
+            continue
+        ok = np.ones(n, dtype=bool)
+        for k in range(dim):
+            ok &= (coord[k] + off[k] >= 0) & (coord[k] + off[k] < g)
+        r = np.nonzero(ok)[0]
+        c = np.zeros(r.size, dtype=np.int64)
+        for k in range(dim):
+            c += (coord[k][r] + off[k]) * g ** k
+        rows.append(r)
+        cols.append(c)
+        vals.append(np.full(r.size, float(nb) if not any(off) else -1.0))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    v = np.concatenate(vals)
+    order = np.lexsort((c, r))
+    return Csr(n, n, _row_ptr(np.bincount(r, minlength=n)), c[order].astype(np.int32),
+               v[order].astype(dtype))
+
+
+def aggregates(g, dim):
+    """Aggregate of every fine point of the g^dim grid: blocks of 2 points per
+    side (the last block of an odd side holds one), coarse index
+    X + h*Y (+ h^2*Z) with h = ceil(g/2) coarse points per side."""
+    h = (g + 1) // 2
+    f = np.arange(g ** dim, dtype=np.int64)
+    agg = np.zeros(f.size, dtype=np.int64)
+    for k in range(dim):
+        agg += ((f // g ** k) % g // 2) * h ** k
+    return agg, h ** dim
+
+
+def aggregation_p_grid(g, dim, dtype=np.float64) -> Csr:
+    """Piecewise-constant prolongation of unsmoothed aggregation: fine point
+    i -> its aggregate, value 1."""
+    agg, nc = aggregates(g, dim)
+    n = agg.size
+    return Csr(n, nc, _row_ptr(np.ones(n, dtype=np.int64)), agg.astype(np.int32),
+               np.ones(n, dtype=dtype))
+
+
+def aggregation_r_grid(g, dim, dtype=np.float64) -> Csr:
+    """Restriction R = P^T, built directly: coarse row I lists the fine points
+    of aggregate I in ascending fine index, value 1."""
+    agg, nc = aggregates(g, dim)
+    fine = np.arange(agg.size, dtype=np.int64)
+    order = np.lexsort((fine, agg))
+    return Csr(nc, agg.size, _row_ptr(np.bincount(agg, minlength=nc)),
+               fine[order].astype(np.int32), np.ones(agg.size, dtype=dtype))
+
+
+# Galerkin problems of the multigrid experiment: name -> (dim, points, grid
+# points per side at the measured size)
+GALERKIN = {"2d-5pt": (2, 5, 1024), "2d-9pt": (2, 9, 1024), "3d-7pt": (3, 7, 101),
+            "3d-27pt": (3, 27, 101)}
+
+
+def galerkin(name, g=None, dtype=np.float64):
+    """(A, P, R) of a Galerkin product R*A*P: the named stencil and
+    unsmoothed 2^dim aggregation, at g points per side (default: the
+    measured size)."""
+    dim, points, g0 = GALERKIN[name]
+    g = g0 if g is None else g
+    return (stencil(g, dim, points, dtype), aggregation_p_grid(g, dim, dtype),
+            aggregation_r_grid(g, dim, dtype))
 
 
 def banded_csr(n, dmin, dmax, band_frac, rng, dtype) -> Csr:

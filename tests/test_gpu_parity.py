@@ -105,6 +105,32 @@ def test_config3_chain_full():
     check(R, AP)
 
 
+def _galerkin_orders(name, g, dtype):
+    """R*(A*P) and (R*A)*P on the GPU, every product checked against the
+    oracle; the two orders must agree bit for bit (small-integer values make
+    every sum exact)."""
+    from synthetic import Csr
+    A, P, R = S.galerkin(name, g, dtype)
+    (rp, ci, v), _ = check(A, P)
+    (rp1, ci1, v1), _ = check(R, Csr(A.rows, P.cols, rp, ci, v))
+    (rp, ci, v), _ = check(R, A)
+    (rp2, ci2, v2), _ = check(Csr(R.rows, A.cols, rp, ci, v), P)
+    assert np.array_equal(rp1, rp2) and np.array_equal(ci1, ci2) and np.array_equal(v1, v2)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("name,g", [("2d-5pt", 301), ("2d-9pt", 256), ("3d-7pt", 33),
+                                    ("3d-27pt", 30)])
+def test_galerkin_orders(name, g, dtype):
+    _galerkin_orders(name, g, dtype)
+
+
+@pytest.mark.parametrize("name", ["2d-5pt", "2d-9pt", "3d-7pt", "3d-27pt"])
+def test_galerkin_orders_full(name):
+    """The multigrid experiment's sizes (1024^2 and 101^3 grids)."""
+    _galerkin_orders(name, None, np.float64)
+
+
 @pytest.mark.parametrize("n", [2000, 20000])
 def test_config5_scaled_f32(n):
     A, B = S.config5(n=n, ncols=512)

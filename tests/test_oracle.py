@@ -259,6 +259,91 @@ def test_galerkin_closed_form_full():
     assert np.array_equal(RAP.col_idx, c2) and np.array_equal(RAP.val, v2)
 
 
+def _coarse_interior(dim, points):
+    """Row of R*A*P for an aggregate whose neighbouring aggregates are all
+    full 2^dim blocks, as {offset: value}, derived by hand.  Entry (I, J) is
+    the sum of a_ij over fine i in I and j in J.  For the full stencil
+    (3^dim points) the coupled fine pairs factor over the dimensions: along
+    one axis a 2-block couples to itself through 4 ordered pairs and to a
+    neighbouring block through 1, so J at offset D != 0 gets -prod_k c(D_k)
+    with c(0) = 4, c(+-1) = 1, and the diagonal is 2^dim (3^dim - 1) minus the
+    4^dim - 2^dim coupled pairs of distinct points inside the block.  For the
+    axis stencil (2 dim + 1 points) only blocks at a unit axis offset couple,
+    through the 2^(dim-1) fine edges that cross the shared face; the diagonal
+    is 2^dim * 2 dim minus the dim * 2^dim ordered edges inside the block."""
+    import itertools
+    out = {}
+    for off in itertools.product((-1, 0, 1), repeat=dim):
+        nz = sum(abs(o) for o in off)
+        if points == 3 ** dim:
+            if nz == 0:
+                out[off] = 2 ** dim * (3 ** dim - 1) - (4 ** dim - 2 ** dim)
+            else:
+                out[off] = -int(np.prod([1 if o else 4 for o in off]))
+        else:
+            if nz == 0:
+                out[off] = dim * 2 ** dim
+            elif nz == 1:
+                out[off] = -(2 ** (dim - 1))
+    return out
+
+
+GALERKIN_SMALL = [("2d-5pt", 8), ("2d-5pt", 9), ("2d-9pt", 8), ("2d-9pt", 11),
+                  ("3d-7pt", 6), ("3d-7pt", 7), ("3d-27pt", 6), ("3d-27pt", 9)]
+
+
+@pytest.mark.parametrize("name,g", GALERKIN_SMALL)
+def test_galerkin_variants(name, g):
+    """Both multiplication orders of R*A*P for every stencil of the
+    multigrid experiment (odd g leaves one-point aggregates on the far
+    faces): equal bit for bit (small integers, every sum exact), equal to
+    the dense triple product, and interior rows equal to the hand-derived
+    coarse stencil."""
+    import itertools
+    from synthetic import Csr
+    dim, points, _ = S.GALERKIN[name]
+    A, P, R = S.galerkin(name, g)
+    AP = oracle.spgemm(T(A), T(P))
+    RAP1 = oracle.spgemm(T(R), (AP.rows, AP.cols, AP.row_ptr.astype(np.int32), AP.col_idx, AP.val))
+    RA = oracle.spgemm(T(R), T(A))
+    RAP2 = oracle.spgemm((RA.rows, RA.cols, RA.row_ptr.astype(np.int32), RA.col_idx, RA.val), T(P))
+    assert np.array_equal(RAP1.row_ptr, RAP2.row_ptr)
+    assert np.array_equal(RAP1.col_idx, RAP2.col_idx)
+    assert np.array_equal(RAP1.val, RAP2.val)
+    # dense triple product (BLAS) and the boolean pattern product
+    dense = R.to_dense() @ A.to_dense() @ P.to_dense()
+    pat = (R.pattern_dense().astype(np.int64) @ A.pattern_dense().astype(np.int64)
+           @ P.pattern_dense().astype(np.int64)) > 0
+    C = Csr(RAP1.rows, RAP1.cols, RAP1.row_ptr, RAP1.col_idx, RAP1.val)
+    assert np.array_equal(C.pattern_dense(), pat)
+    assert np.array_equal(C.to_dense(), dense)
+    # interior aggregates: X in [1, (g - 3) // 2] along every axis
+    h = (g + 1) // 2
+    want = _coarse_interior(dim, points)
+    inner = range(1, (g - 3) // 2 + 1)
+    count = 0
+    for X in itertools.product(inner, repeat=dim):
+        I = sum(X[k] * h ** k for k in range(dim))
+        a, b = RAP1.row_ptr[I], RAP1.row_ptr[I + 1]
+        got = {}
+        for c, v in zip(RAP1.col_idx[a:b], RAP1.val[a:b]):
+            off = tuple(int((c // h ** k) % h) - X[k] for k in range(dim))
+            got[off] = v
+        assert got == want, (I, got)
+        assert sum(got.values()) == 0
+        count += 1
+    assert count > 0
+
+
+def test_stencil_generator_matches_27_point():
+    """The general generator reproduces workload 3's matrices exactly."""
+    A, P, R = S.galerkin("3d-27pt", 8)
+    for X, Y in ((A, S.stencil27(8)), (P, S.aggregation_p(8)), (R, S.aggregation_r(8))):
+        assert np.array_equal(X.row_ptr, Y.row_ptr)
+        assert np.array_equal(X.col_idx, Y.col_idx)
+        assert np.array_equal(X.val, Y.val)
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_f32_accumulator(seed):
     """The binary32 variant stays within the binary32 dot-product bound of the
