@@ -19,19 +19,26 @@
 //  * at the end L1 is merged into G once more, or, if G was never used,
 //    written out directly.
 //
-// Splitting (so that rows far longer than the average are balanced):
-//  * phase 1 (k_long): a row is cut into product segments; each segment is
-//    a work item that leaves a sorted, duplicate-free partial.  A row with a
-//    single segment is finished here: its result goes to its 256-entry C~
-//    slot, or to a pool block of 256 * 2^k entries.
-//  * phase 2 (k_combine): for rows with several segments, one work-group per
-//    column range folds that range of every partial, in segment order, into
-//    one output piece with the same merge method.  Phase 1 records where
-//    every range starts in every partial, so phase 2 needs no search.
+// Splitting (so that rows far longer than the average are balanced): a row
+// of up to 1024 products is one work item; a longer row is cut into product
+// segments of 512 (more when it would need over 512 segments).
+//  * phase 1: every item by one wavefront (k_long_w: a pass with 512-entry
+//    tiles, then one with 1024-entry tiles over the items it listed), by a
+//    work-group radix sort in LDS up to 4096 products (k_long1), else by the
+//    merge method above (k_long).  An item of a split row writes its
+//    products sorted on (column, position) but not folded, and where every
+//    output column range starts in them; a one-item row is folded straight
+//    into a place of its own.
+//  * phase 2: for split rows, every column range of the row (about 256
+//    entries) gathers its part of every segment in segment order, sorts it
+//    on (column, stream index) and folds it, with the same cascade of
+//    wavefront (k_combine_w), work-group (k_combine1) and merge-method
+//    (k_combine) kernels.
 //
-// Values of items that neither spill nor are split are Gustavson's
-// sequential sums exactly; otherwise partial sums are added in segment order
-// (rounding may differ, the order is deterministic).
+// Products of one column are thus added in Gustavson's order (ascending j)
+// from +0.0, exactly as a sequential sum, except where the merge method
+// handles the work (items or ranges above 4096 entries, or splitting turned
+// off): there partial sums are added in segment order, deterministically.
 #include <algorithm>
 
 #include "common.hpp"
