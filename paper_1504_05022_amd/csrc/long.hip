@@ -1561,6 +1561,11 @@ template <int K> DEVI int wix(int l) { return (l & (K - 1)) * WAVE + (l >> Log2<
 // are both free of LDS bank conflicts.  A tile needs U + U / 64 slots.
 DEVI int wpad(int r) { return r + (r >> 6); }
 
+// Wavefronts per SIMD that the tile's LDS allows (FP64 values): the register
+// budget of the wavefront kernels is held to it, since they wait on memory
+// and need every resident wavefront they can get.
+template <int K> constexpr int wave_occupancy() { return K <= 8 ? 5 : 3; }
+
 template <typename T, int K, typename Key>
 DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
                     unsigned char *lds_a, T *lds_b) {
@@ -1582,21 +1587,28 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) rs[kk * WAVE + pos] = -1;
   wave_sync();
-  // run starts of the b_j* rows that overlap [p0, p1)
-  for (int32_t e = item.e_first + pos; e < e1; e += WAVE) {
-    const int64_t s0 = a.e.P[e] - pbase;
-    if (s0 >= p1) break;
-    const int64_t s1 = a.e.P[e + 1] - pbase;
-    if (s1 > p0 && s1 > s0) {
+  // run starts of the b_j* rows that overlap [p0, p1); the loads of a
+  // chunk of 64 entries are issued together (clamped, not branched on)
+  const GLOBAL_AS int64_t *gP = as_global(a.e.P);
+  for (int32_t e0 = item.e_first; e0 < e1; e0 += WAVE) {
+    const int32_t e = e0 + pos;
+    const bool in = e < e1;
+    const int32_t ec = in ? e : e1 - 1;
+    const int64_t s0 = gP[ec] - pbase;
+    const int64_t s1 = gP[ec + 1] - pbase;
+    const int32_t j = as_global(a.e.acol)[ec];
+    const T av = as_global(a.e.aval)[ec];
+    if (in && s0 < p1 && s1 > p0 && s1 > s0) {
       int64_t ls = s0 - p0;
       int32_t off = 0;
       if (ls < 0) {
         off = static_cast<int32_t>(-ls);
         ls = 0;
       }
-      rs[wix<K>(static_cast<int>(ls))] = a.e.brp[a.e.acol[e]] + off;
-      ra[wix<K>(static_cast<int>(ls))] = a.e.aval[e];
+      rs[wix<K>(static_cast<int>(ls))] = as_global(a.e.brp)[j] + off;
+      ra[wix<K>(static_cast<int>(ls))] = av;
     }
+    if (!__any(in && s1 < p1)) break;  // the next chunk starts at or after p1
   }
   wave_sync();
   int st[K];
@@ -1636,19 +1648,28 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
     }
   }
   wave_sync();
+  // every load of the tile is issued before any is used: positions past
+  // the end load B's entry 0 (there are products, so B has one) and are
+  // then ignored
+  int32_t bc[K];
+  T bv[K], av[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = kk * WAVE + pos;
+    const int32_t g = gb[l];
+    const int32_t bidx = l < tn ? g : 0;
+    av[kk] = ga[l];
+    bc[kk] = as_global(a.e.bcol)[bidx];
+    bv[kk] = as_global(a.e.bval)[bidx];
+  }
   Key key[K];
   T prod[K];
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     const int l = kk * WAVE + pos;
-    key[kk] = KMAX;
-    prod[kk] = T(0);
-    if (l < tn) {
-      const int32_t bidx = gb[l];
-      const int32_t c = a.e.bcol[bidx];
-      prod[kk] = ga[l] * a.e.bval[bidx];
-      key[kk] = (static_cast<Key>(c) << LOGU) | static_cast<Key>(l);
-    }
+    const bool ok = l < tn;
+    prod[kk] = ok ? av[kk] * bv[kk] : T(0);
+    key[kk] = ok ? ((static_cast<Key>(bc[kk]) << LOGU) | static_cast<Key>(l)) : KMAX;
   }
   wave_sync();  // pv takes the place of ga
 #pragma unroll
@@ -1779,7 +1800,8 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
 // Every item (in_list == nullptr), or the listed ones in a grid-stride
 // loop; items above 64 K products go to out_list.
 template <typename T, typename Key, int K>
-__global__ __launch_bounds__(WAVE_NT) void k_long_w(LongArgs<T> a, int64_t nitems,
+__global__ __launch_bounds__(WAVE_NT) __attribute__((amdgpu_waves_per_eu(wave_occupancy<K>())))
+void k_long_w(LongArgs<T> a, int64_t nitems,
                                                     const unsigned int *in_list,
                                                     const unsigned int *in_cnt,
                                                     unsigned int *out_list,
@@ -1823,64 +1845,92 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
   const int32_t c0 = b << lr.shift;
   const int32_t nseg = lr.nseg;
   const int32_t *ptab = a.split + lr.sbase;
-  // segment table (in the tile buffers, dead before they are used): first
-  // stream index of every segment, and the partial-buffer index of stream
-  // index 0 for it
-  int32_t *toff = reinterpret_cast<int32_t *>(lds_a);
-  int32_t *tbase = reinterpret_cast<int32_t *>(lds_b);
-  int64_t carry = 0, obase = 0;
-  for (int32_t s0 = 0; s0 < nseg; s0 += WAVE) {
-    const int32_t s = s0 + pos;
-    int64_t len = 0, lo = 0;
-    if (s < nseg) {
-      const int64_t cnt = a.partials[lr.item0 + s].cnt;
-      lo = ptab[static_cast<int64_t>(b) * nseg + s];
-      int64_t hi = ptab[static_cast<int64_t>(b + 1) * nseg + s];
-      lo = lo < 0 ? 0 : (lo > cnt ? cnt : lo);
-      hi = hi < lo ? lo : (hi > cnt ? cnt : hi);
-      len = hi - lo;
-    }
-    const int64_t incl = group_incl_sum<WAVE>(len);
-    const int64_t ex = carry + incl - len;
-    if (s < nseg) {
-      toff[s] = static_cast<int32_t>(ex < U ? ex : U);
-      tbase[s] = static_cast<int32_t>(static_cast<int64_t>(s) * lr.segp + lo - ex);
-    }
-    carry += group_last<WAVE>(incl);
-    obase += group_last<WAVE>(group_incl_sum<WAVE>(lo));
+  // segment table: lane p holds segments p*KS .. p*KS+KS-1, whose range
+  // bounds are loaded together (one memory round trip); the stream is the
+  // concatenation of the segments' parts of the range, in segment order
+  constexpr int KS = MAXS / WAVE;
+  static_assert(MAXS % WAVE == 0, "segment table rows must fill lanes evenly");
+  const GLOBAL_AS int32_t *lo_row = as_global(ptab + static_cast<int64_t>(b) * nseg);
+  const GLOBAL_AS int32_t *hi_row = as_global(ptab + static_cast<int64_t>(b + 1) * nseg);
+  int32_t slo[KS], slen[KS];
+#pragma unroll
+  for (int j = 0; j < KS; ++j) {
+    const int32_t sg = pos * KS + j;
+    const int32_t sc = sg < nseg ? sg : nseg - 1;
+    slo[j] = lo_row[sc];
+    slen[j] = hi_row[sc];
   }
-  const int64_t E = carry;
+  int32_t tot_len = 0, tot_lo = 0;
+#pragma unroll
+  for (int j = 0; j < KS; ++j) {
+    const bool in = pos * KS + j < nseg;
+    const int32_t lo = in ? max(slo[j], 0) : 0;
+    slen[j] = in ? max(slen[j] - lo, 0) : 0;
+    slo[j] = lo;
+    tot_len += slen[j];
+    tot_lo += lo;
+  }
+  // one scan for both sums (each below 2^31, so the halves never carry):
+  // stream length and this lane's first stream index in the low half, the
+  // sum of the range starts (where this range's output begins) in the high
+  const int64_t packed = (static_cast<int64_t>(tot_lo) << 32) | static_cast<uint32_t>(tot_len);
+  const int64_t incl = group_incl_sum<WAVE>(packed);
+  const int64_t last = group_last<WAVE>(incl);
+  const int64_t E = last & 0xffffffffll;
+  const int64_t obase = last >> 32;
   if (E > U) {
     if (pos == 0) olist[atomicAdd(ocnt, 1u)] = static_cast<unsigned int>(pid);
     return;
   }
-  wave_sync();
   const int tn = static_cast<int>(E);
+  // seg_at[t] = segment whose part starts at stream index t (non-empty parts
+  // start at distinct indices), tbase[s] = partial-buffer index of stream
+  // index 0 for segment s; both in the tile buffers, dead before those are
+  // used
+  int32_t *seg_at = reinterpret_cast<int32_t *>(lds_a);
+  int32_t *tbase = reinterpret_cast<int32_t *>(lds_b);
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) seg_at[pos * K + kk] = -1;
+  wave_sync();
+  {
+    int32_t run = static_cast<int32_t>((incl - packed) & 0xffffffffll);
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+      const int32_t sg = pos * KS + j;
+      if (sg < nseg) {
+        tbase[sg] = static_cast<int32_t>(static_cast<int64_t>(sg) * lr.segp + slo[j] - run);
+        if (slen[j] > 0) seg_at[run] = sg;
+      }
+      run += slen[j];
+    }
+  }
+  wave_sync();
   const int32_t *pcol = a.pcol + lr.pbase;
   const T *pval = a.pval + lr.pbase;
-  // partial-buffer index of every stream entry, found in lane-blocked order
-  // (one search, then a walk) and handed over through LDS so that the loads
-  // below read consecutive entries with consecutive lanes
+  // partial-buffer index of every stream entry: the segment is the last one
+  // starting at or before it (a max-scan in lane-blocked order), handed over
+  // through LDS so that the loads below read consecutive entries with
+  // consecutive lanes
   int32_t gix[K];
   {
-    const int g0 = pos * K;
-    int lo = 0, hi = nseg;  // last segment starting at or before g0
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (toff[mid] <= g0)
-        lo = mid;
-      else
-        hi = mid;
-    }
-    int sg = lo;
+    int run = -1;
+    int sgk[K];
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) {
       const int l = pos * K + kk;
-      gix[kk] = 0;
-      if (l < tn) {
-        while (sg + 1 < nseg && toff[sg + 1] <= l) ++sg;
-        gix[kk] = tbase[sg] + l;
-      }
+      const int v = seg_at[l];
+      run = max(run, l < tn ? v : -1);
+      sgk[kk] = run;
+    }
+    const int inc = group_incl_max<WAVE>(run);
+    int prev = __shfl_up(inc, 1, WAVE);
+    if (pos == 0) prev = -1;
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      const int l = pos * K + kk;
+      const int sg = max(prev, sgk[kk]);
+      const int32_t tb = tbase[sg > 0 ? sg : 0];
+      gix[kk] = l < tn ? tb + l : 0;
     }
   }
   int32_t *gi = reinterpret_cast<int32_t *>(lds_a);
@@ -1891,6 +1941,18 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
     if (l < tn) gi[l] = gix[kk];
   }
   wave_sync();
+  // every load is issued before any is used (entries past the end reload
+  // entry 0 and are ignored)
+  int32_t cv[K];
+  T vv[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = kk * WAVE + pos;
+    const int32_t g = gi[l];
+    const int32_t idx = l < tn ? g : 0;
+    cv[kk] = as_global(pcol)[idx];
+    vv[kk] = as_global(pval)[idx];
+  }
   Key key[K];
   T *pv = lds_b;
 #pragma unroll
@@ -1898,9 +1960,8 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
     const int l = kk * WAVE + pos;
     key[kk] = KMAX;
     if (l < tn) {
-      const int64_t idx = gi[l];
-      pv[l] = pval[idx];
-      key[kk] = (static_cast<Key>(pcol[idx] - c0) << LOGU) | static_cast<Key>(l);
+      pv[l] = vv[kk];
+      key[kk] = (static_cast<Key>(cv[kk] - c0) << LOGU) | static_cast<Key>(l);
     }
   }
   Key *sk = reinterpret_cast<Key *>(lds_a);
@@ -1959,7 +2020,8 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
 // Every piece (in_list == nullptr), or the listed ones in a grid-stride
 // loop; pieces above 64 K entries go to out_list.
 template <typename T, typename Key, int MAXS, int K>
-__global__ __launch_bounds__(WAVE_NT) void k_combine_w(LongArgs<T> a, int64_t npieces,
+__global__ __launch_bounds__(WAVE_NT) __attribute__((amdgpu_waves_per_eu(wave_occupancy<K>())))
+void k_combine_w(LongArgs<T> a, int64_t npieces,
                                                        const unsigned int *in_list,
                                                        const unsigned int *in_cnt,
                                                        unsigned int *out_list,
