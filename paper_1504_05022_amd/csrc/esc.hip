@@ -15,9 +15,14 @@
 
 namespace spg {
 
+// Wavefronts per SIMD kept resident: the kernel waits on memory, so the
+// register budget of the 8-products-per-lane tiles is held to 5 (LDS allows
+// 6 for FP64); not for whole-wavefront rows, which would spill at 5.
+template <int G, int K> constexpr int esc_occupancy() { return K >= 8 && G < 64 ? 5 : 1; }
+
 template <typename T, int G, int K, typename Key>
-__global__ __launch_bounds__(ESC_NT) void k_esc(EscArgs<T> a, const int32_t *rows,
-                                                int64_t nrows) {
+__global__ __launch_bounds__(ESC_NT) __attribute__((amdgpu_waves_per_eu(esc_occupancy<G, K>())))
+void k_esc(EscArgs<T> a, const int32_t *rows, int64_t nrows) {
   using Sh = EscShape<T, G, K, Key>;
   __shared__ __align__(16) unsigned char lds[Sh::lds_bytes];
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * Sh::RPB; base < nrows;

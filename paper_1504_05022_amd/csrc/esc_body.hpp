@@ -71,14 +71,18 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) rs[kk * G + pos] = -1;
   wave_sync();
-  // run starts: entry e of row i contributes products [P[e]-P[e0], P[e+1]-P[e0])
-  for (int32_t e = e0 + pos; e < e1; e += G) {
-    const int64_t s0 = gP[e] - pbase;
-    const int64_t w = gP[e + 1] - gP[e];
-    if (w > 0) {
-      const int32_t j = gacol[e];
-      rs[ix(static_cast<int>(s0))] = gbrp[j];
-      ra[ix(static_cast<int>(s0))] = gaval[e];
+  // run starts: entry e of row i contributes products [P[e]-P[e0], P[e+1]-P[e0]);
+  // the loads of G entries are issued together (clamped, not branched on)
+  for (int32_t eb = e0; eb < e1; eb += G) {
+    const int32_t e = eb + pos;
+    const bool in = e < e1;
+    const int32_t ec = in ? e : e1 - 1;
+    const int64_t q0 = gP[ec], q1 = gP[ec + 1];
+    const int32_t j = gacol[ec];
+    const T av = gaval[ec];
+    if (in && q1 > q0) {
+      rs[ix(static_cast<int>(q0 - pbase))] = gbrp[j];
+      ra[ix(static_cast<int>(q0 - pbase))] = av;
     }
   }
   wave_sync();
@@ -122,21 +126,36 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
     }
   }
   wave_sync();
+  // every load of the row is issued before any is used: positions past the
+  // end load B's entry 0 (a row with products implies that B has one) and
+  // are then ignored
+  int32_t bc[K];
+  T bv[K], av[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    bc[kk] = 0;
+    bv[kk] = T(0);
+    av[kk] = T(0);
+  }
+  if (u > 0) {
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      const int l = kk * G + pos;
+      const int32_t g = gb[l];
+      const int32_t bidx = l < u ? g : 0;
+      av[kk] = ga[l];
+      bc[kk] = gbcol[bidx];
+      bv[kk] = gbval[bidx];
+    }
+  }
   Key key[K];
   T prod[K];
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     const int l = kk * G + pos;
-    key[kk] = KMAX;
-    prod[kk] = T(0);
-    if (l < u) {
-      const int32_t bidx = gb[l];
-      const T av = ga[l];
-      const int32_t c = gbcol[bidx];
-      const T bv = gbval[bidx];
-      prod[kk] = av * bv;
-      key[kk] = (static_cast<Key>(c) << LOGU) | static_cast<Key>(l);
-    }
+    const bool ok = l < u;
+    prod[kk] = ok ? av[kk] * bv[kk] : T(0);
+    key[kk] = ok ? ((static_cast<Key>(bc[kk]) << LOGU) | static_cast<Key>(l)) : KMAX;
   }
   wave_sync();  // pv takes the place of ga
 #pragma unroll
