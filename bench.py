@@ -269,6 +269,30 @@ def extensions(args, torch, S, L):
     return out
 
 
+def tiny_rows_ablation(torch, L, dA, nrows, reps=5):
+    """Bin group 3 (rows of 2..32 products) of the headline workload: the
+    wavefront ESC against the paper's heap method (one thread per row, one
+    kernel per exact size), stage time from the library's event timers and
+    whole-step time."""
+    tiny = 1 << L.STAGES.index("tiny")
+    res = {"rows": nrows}
+    for key, heap in (("wavefront_esc", 0), ("heap_method", 1)):
+        stage = 0.0
+        L.spgemm(dA, dA, tiny_heap=heap)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            C, info = L.spgemm(dA, dA, return_info=True, timing=1, timing_mask=tiny, tiny_heap=heap)
+            stage += float(info.stage_ms[L.STAGES.index("tiny")])
+            del C
+        torch.cuda.synchronize()
+        res[key] = {"stage_ms": round(stage / reps, 4),
+                    "step_ms": round((time.perf_counter() - t0) * 1e3 / reps, 4)}
+    res["heap_over_esc"] = round(res["heap_method"]["stage_ms"] /
+                                 max(res["wavefront_esc"]["stage_ms"], 1e-9), 3)
+    return res
+
+
 def galerkin_orders(torch, S, L, reps):
     """R*(A*P) against (R*A)*P for the 2D 5-/9-point (1024^2) and 3D
     7-/27-point (101^3) stencils with unsmoothed 2^d aggregation, binary64:
@@ -426,9 +450,11 @@ def main():
                                "sample": "the full workload once (%.1f s)" % dt}
         del ref
     if not args.no_ext:
+        tiny = tiny_rows_ablation(torch, L, dA, int(sum(info.bin_count[2:33])))
         del dA
         torch.cuda.empty_cache()
         out["extensions"] = extensions(args, torch, S, L)
+        out["extensions"]["tiny_rows"] = tiny
     print(json.dumps(out), flush=True)
 
 

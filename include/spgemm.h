@@ -110,6 +110,11 @@ typedef struct {
                            timed stage adds two event records to the stream,
                            and spgemm_compute waits for the end of the last
                            timed stage before it returns                     */
+  int32_t tiny_heap;    /* nonzero: rows of sizes 2..bin_edges[0] use the
+                           paper's heap method (one thread per row, one
+                           kernel per exact size) instead of the wavefront
+                           ESC; duplicates are then added in heap order, so
+                           values may round differently (plain path only)   */
 } spgemm_options;
 
 #define SPGEMM_NBINS 38

@@ -591,7 +591,14 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
 
   // ---- stage 3, bin groups 2-3: one launch per power-of-two capacity
   stage_begin(p, SPGEMM_T_TINY, s);
-  {
+  if (p->opt.tiny_heap) {
+    // bin 1 through the wavefront kernel, bins 2..edge[0] one kernel each
+    if (launch_esc<T>(ea, p->binlist + S.bin_off[1], S.bin_off[2] - S.bin_off[1], 1, p->n, s))
+      return fail(SPGEMM_EINVAL, "no ESC kernel for this capacity");
+    for (int b = 2; b <= p->be.e[0]; ++b)
+      if (launch_heap<T>(ea, p->binlist + S.bin_off[b], S.bin_off[b + 1] - S.bin_off[b], b, s))
+        return fail(SPGEMM_EINVAL, "no heap kernel for this size");
+  } else {
     int b = 1;
     while (b <= p->be.e[0]) {
       const int cap = static_cast<int>(next_pow2(b));

@@ -254,6 +254,11 @@ template <typename T>
 int launch_esc(const EscArgs<T> &a, const int32_t *rows, int64_t nrows, int cap, int64_t ncols,
                hipStream_t s);
 
+// Rows of one exact size 2..32 with the paper's one-thread heap method
+// (bin group 3); returns -1 for other sizes.
+template <typename T>
+int launch_heap(const EscArgs<T> &a, const int32_t *rows, int64_t nrows, int usz, hipStream_t s);
+
 template <typename T> struct LongArgs {
   EscArgs<T> e;
   const LongRow *lrows;

@@ -46,7 +46,8 @@ class Options(ctypes.Structure):
     _fields_ = [("bin_edges", ctypes.c_int32 * 5), ("long_slot", ctypes.c_int32),
                 ("l1_cap", ctypes.c_int32), ("seg", ctypes.c_int64),
                 ("pool_entries", ctypes.c_int64), ("validate", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("timing_mask", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("timing_mask", ctypes.c_int32),
+                ("tiny_heap", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -77,6 +77,32 @@ def test_bin_edges(dtype, col_range):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("col_range", [None, 6])
+@pytest.mark.parametrize("edge0", [32, 16])
+def test_tiny_rows_heap_method(dtype, col_range, edge0):
+    """The paper's heap method for bin group 3 (one thread per row, one
+    kernel per exact size): structure bit for bit, values within tolerance
+    (duplicates are added in heap order); few distinct columns exercise the
+    fusing step; every other bin is unchanged."""
+    targets = list(range(0, 40)) + ([100, 700, 3000] if col_range is None else [60])
+    A, B = S.crafted_rows(targets * 20, col_range=col_range, empty_refs=1, dtype=dtype)
+    edges = (edge0, 64, 128, 256, 512)
+    (rp0, ci0, v0), i0 = check(A, B, exact=False, bin_edges=edges)
+    (rp1, ci1, v1), i1 = check(A, B, exact=False, bin_edges=edges, tiny_heap=1)
+    assert np.array_equal(rp0, rp1) and np.array_equal(ci0, ci1)
+    assert list(i0.bin_count) == list(i1.bin_count)
+    # rows outside bin group 3 are computed exactly as before
+    c = oracle.spgemm(A.astype(np.float64).as_tuple(), B.astype(np.float64).as_tuple())
+    keep = np.repeat((c.u < 2) | (c.u > edge0), np.diff(c.row_ptr))
+    assert np.array_equal(v0[keep], v1[keep])
+
+
+def test_tiny_rows_heap_method_scaled():
+    A, _ = S.config2(n=20000, cap=400)
+    check(A, A, exact=False, tiny_heap=1)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_long_rows_that_spill(dtype):
     """Results longer than the LDS level-1 sequence: spills into growing pool
     blocks (values then within tolerance, structure exact)."""
