@@ -261,12 +261,69 @@ def extensions(args, torch, S, L):
     except Exception as e:
         out["backward"] = {"error": repr(e)[:300]}
     torch.cuda.empty_cache()
+    # ---- merge-algorithm microbenchmark (five algorithms, three entry types)
+    try:
+        out["merge"] = merge_microbench(torch, L)
+    except Exception as e:
+        out["merge"] = {"error": repr(e)[:300]}
+    torch.cuda.empty_cache()
     # ---- Galerkin products R*A*P of the multigrid experiment, both orders
     try:
         out["galerkin"] = galerkin_orders(torch, S, L, reps)
     except Exception as e:
         out["galerkin"] = {"error": repr(e)[:300]}
     return out
+
+
+def merge_microbench(torch, L, total_log2=25, reps=3):
+    """Merging 2^25 entries as pairs of sorted runs of length l = 2^4..2^13
+    with each of the five algorithms, for 32-bit keys alone and with 32- or
+    64-bit values: the best rate (Gentries/s, inputs and outputs in HBM) over
+    work-group sizes 64..1024 and the size that gave it, and the fastest
+    algorithm per (entry type, l)."""
+    total = 1 << total_log2
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(150405022)
+    keys0 = torch.randint(0, 1 << 31, (total,), dtype=torch.int32, device="cuda", generator=gen)
+    res = {}
+    for vb, name in ((0, "key32"), (4, "key32_val32"), (8, "key32_val64")):
+        vals = None if vb == 0 else torch.arange(total, dtype=torch.int32 if vb == 4 else torch.int64,
+                                                   device="cuda")
+        per = {}
+        for lg in range(4, 14):
+            l = 1 << lg
+            keys = keys0.view(-1, l).sort(dim=1).values.reshape(-1).contiguous()
+            row = {}
+            for alg in L.MERGE_ALGORITHMS:
+                best = None
+                for nt in (64, 128, 256, 512, 1024):
+                    tile = max(2 * l, 2 * nt)
+                    if alg == "merge_path" and tile // nt > 32:
+                        continue
+                    if tile * (4 + vb) * (2 if alg == "ranking" else 1) > 160 * 1024:
+                        continue
+                    L.merge_pairs(keys, vals, l, alg, nt)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(reps):
+                        L.merge_pairs(keys, vals, l, alg, nt)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / reps
+                    if best is None or ms < best[0]:
+                        best = (ms, nt)
+                if best is not None:
+                    row[alg] = {"gentries_s": round(total / (best[0] * 1e-3) / 1e9, 2),
+                                "threads": best[1]}
+            if row:
+                row["fastest"] = max(row, key=lambda a: row[a]["gentries_s"])
+            else:
+                row["fastest"] = None  # no tile of 2l entries fits in LDS
+            per["l=2^%d" % lg] = row
+            del keys
+        res[name] = per
+        del vals
+    return res
 
 
 def tiny_rows_ablation(torch, L, dA, nrows, reps=5):

@@ -257,6 +257,31 @@ int spgemm_batch_stats_get(spgemm_batch batch, spgemm_batch_stats *stats);
 /* Release the graph, the plans and the outputs. */
 int spgemm_batch_destroy(spgemm_batch batch);
 
+/*
+ * Merge-algorithm microbenchmark (Section 3.2, Fig. 5): merge `pairs`
+ * pairs of sorted sequences, each pair stored as 2l consecutive entries
+ * (first sequence, then second, both ascending), into ascending order, in
+ * LDS, with one of the five algorithms the paper compares.  Keys are 32-bit
+ * unsigned; value_bytes = 0 (keys only), 4 or 8 (a value moves with each
+ * key).  l is a power of two; `threads` (64..1024, a power of two) is the
+ * work-group size, and a work-group merges max(2l, 2 threads) entries.
+ * Ranking merge and merge path keep entries of the first sequence first
+ * among equal keys; the networks may order equal keys either way.  Device
+ * pointers; outputs must not overlap inputs.  Returns SPGEMM_EINVAL when the
+ * tile does not fit in 160 KB of LDS or when merge path would hold more
+ * than 32 outputs per thread.  Asynchronous on `stream`.
+ */
+enum {
+  SPGEMM_MERGE_RANKING = 0,     /* ranking merge (out of place)              */
+  SPGEMM_MERGE_PATH = 1,        /* merge path                                 */
+  SPGEMM_MERGE_ODDEVEN = 2,     /* Batcher's odd-even merging network         */
+  SPGEMM_MERGE_BITONIC = 3,     /* bitonic merging network                    */
+  SPGEMM_MERGE_BITONIC_ADV = 4  /* bitonic, three stages per register pass    */
+};
+int spgemm_merge_pairs(int algorithm, int value_bytes, int64_t l, int64_t pairs, int threads,
+                       const uint32_t *keys_in, const void *vals_in, uint32_t *keys_out,
+                       void *vals_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

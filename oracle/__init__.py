@@ -215,3 +215,19 @@ def value_error(val, ref: OracleResult):
     big &= nz
     plain = float(np.max(d[big] / np.abs(ref_v[big]))) if np.any(big) else 0.0
     return scaled, plain
+
+
+def merge_pairs(keys: np.ndarray, vals, l: int):
+    """Merge of sorted sequences (Section 3.2, the merge microbenchmark):
+    ``keys`` holds pairs of ascending length-``l`` runs, each pair as 2l
+    consecutive entries; every pair comes back in ascending key order, the
+    first run's entries before the second's among equal keys (the stable
+    sort of the pair's entries, a library sort standing for the merge).
+    ``vals`` (or None) moves with the keys.  Returns (keys, vals)."""
+    k = np.asarray(keys).reshape(-1, 2 * l)
+    order = np.argsort(k, axis=1, kind="stable")
+    ko = np.take_along_axis(k, order, axis=1).reshape(-1)
+    if vals is None:
+        return ko, None
+    v = np.asarray(vals).reshape(-1, 2 * l)
+    return ko, np.take_along_axis(v, order, axis=1).reshape(-1)

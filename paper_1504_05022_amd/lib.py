@@ -85,7 +85,7 @@ class BatchStats(ctypes.Structure):
 EXPORTS = ("spgemm_default_options", "spgemm_strerror", "spgemm_last_error", "spgemm_analyze",
            "spgemm_compute", "spgemm_backward", "spgemm_plan_info", "spgemm_plan_destroy",
            "spgemm_batch_create", "spgemm_batch_run", "spgemm_batch_stats_get",
-           "spgemm_batch_destroy")
+           "spgemm_batch_destroy", "spgemm_merge_pairs")
 
 _ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -153,6 +153,9 @@ def load(path: str = LIB_PATH):
     lib.spgemm_batch_stats_get.restype = ctypes.c_int
     lib.spgemm_batch_destroy.argtypes = [P]
     lib.spgemm_batch_destroy.restype = ctypes.c_int
+    lib.spgemm_merge_pairs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_int, P, P, P, P, P]
+    lib.spgemm_merge_pairs.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -311,6 +314,32 @@ def spgemm(A: CsrMatrix, B: CsrMatrix, return_info=False, **kw):
     finally:
         plan.close()
     return (C, info) if return_info else C
+
+
+MERGE_ALGORITHMS = ("ranking", "merge_path", "odd_even", "bitonic", "bitonic_advanced")
+
+
+def merge_pairs(keys: torch.Tensor, vals, l: int, algorithm: str, threads: int = 256):
+    """spgemm_merge_pairs on device tensors: ``keys`` (int32 holding the
+    32-bit unsigned keys) stores pairs of ascending length-``l`` runs, 2l
+    entries per pair; ``vals`` is None or an int32 / int64 tensor of the same
+    length.  Returns new (keys, vals) tensors, every pair merged."""
+    lib = load()
+    if keys.dtype != torch.int32 or not keys.is_cuda:
+        raise TypeError("keys must be a CUDA int32 tensor")
+    n = keys.numel()
+    if n % (2 * l):
+        raise ValueError("keys must hold whole pairs of 2l entries")
+    vb = 0 if vals is None else vals.element_size()
+    if vals is not None and (vals.numel() != n or vb not in (4, 8)):
+        raise ValueError("vals must be None or 4- or 8-byte values, one per key")
+    ko = torch.empty_like(keys)
+    vo = None if vals is None else torch.empty_like(vals)
+    _check(lib.spgemm_merge_pairs(MERGE_ALGORITHMS.index(algorithm), vb, l, n // (2 * l), threads,
+                                  keys.data_ptr(), None if vals is None else vals.data_ptr(),
+                                  ko.data_ptr(), None if vo is None else vo.data_ptr(),
+                                  _stream_handle()))
+    return ko, vo
 
 
 def _view(ptr, nbytes, dtype):

@@ -461,3 +461,41 @@ def test_planted_mistakes_are_caught():
     r2 = np.repeat(np.arange(12), np.diff(C2.row_ptr))
     assert np.array_equal(C1.val, dense1[np.repeat(np.arange(12), np.diff(C1.row_ptr)), C1.col_idx])
     assert not (np.array_equal(C2.col_idx, C1.col_idx) and np.array_equal(C2.val, dense1[r2, C2.col_idx]))
+
+
+def _merge_two_pointer(a, b, av, bv):
+    """Textbook merge of two ascending lists, the first list winning ties."""
+    i = j = 0
+    ok, ov = [], []
+    while i < len(a) or j < len(b):
+        if j >= len(b) or (i < len(a) and a[i] <= b[j]):
+            ok.append(a[i]); ov.append(av[i]); i += 1
+        else:
+            ok.append(b[j]); ov.append(bv[j]); j += 1
+    return ok, ov
+
+
+@pytest.mark.parametrize("l", [1, 2, 3, 8, 33])
+def test_merge_pairs_two_pointer(l):
+    """The oracle's merge equals a two-pointer merge, ties included (keys
+    drawn from a handful of values), pair by pair."""
+    rng = np.random.default_rng(600 + l)
+    pairs = 7
+    k = rng.integers(0, 4, (pairs, 2 * l)).astype(np.uint32)
+    k[:, :l].sort(axis=1)
+    k[:, l:].sort(axis=1)
+    v = np.arange(k.size, dtype=np.int64).reshape(pairs, 2 * l)
+    ko, vo = oracle.merge_pairs(k.reshape(-1), v.reshape(-1), l)
+    for p in range(pairs):
+        ek, ev = _merge_two_pointer(list(k[p, :l]), list(k[p, l:]), list(v[p, :l]), list(v[p, l:]))
+        assert ko[p * 2 * l:(p + 1) * 2 * l].tolist() == ek
+        assert vo[p * 2 * l:(p + 1) * 2 * l].tolist() == ev
+
+
+def test_merge_pairs_worked_example():
+    """A hand-merged pair: ties keep the first run's entry first."""
+    k = np.array([1, 4, 4, 9, 0, 4, 5, 9], np.uint32)
+    v = np.array([10, 11, 12, 13, 20, 21, 22, 23])
+    ko, vo = oracle.merge_pairs(k, v, 4)
+    assert ko.tolist() == [0, 1, 4, 4, 4, 5, 9, 9]
+    assert vo.tolist() == [20, 10, 11, 12, 21, 22, 13, 23]
