@@ -48,11 +48,25 @@ template <int C> DEVI int64_t xcd_block_id() {
 
 // ---------------------------------------------------------------- shuffles
 
+// Value of lane (lane ^ m).  With m known at compile time, distances 1, 2
+// and 8 are DPP moves inside the VALU (quad permutations and a rotation of
+// each row of 16 lanes by 8), 4 and 16 are LDS-unit swizzles inside groups of
+// 32 lanes (no address operand), 32 goes through ds_bpermute.
 DEVI uint32_t shfl_xor_u32(uint32_t v, int m) {
-  return static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), m, WAVE));
+  const int x = static_cast<int>(v);
+  switch (m) {
+    case 1: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
+    case 2: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
+    case 8: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));
+    case 4: return static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(x, 0x1F | (4 << 10)));
+    case 16: return static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(x, 0x1F | (16 << 10)));
+    default: return static_cast<uint32_t>(__shfl_xor(x, m, WAVE));
+  }
 }
 DEVI uint64_t shfl_xor_u64(uint64_t v, int m) {
-  return static_cast<uint64_t>(__shfl_xor(static_cast<long long>(v), m, WAVE));
+  const uint32_t lo = shfl_xor_u32(static_cast<uint32_t>(v), m);
+  const uint32_t hi = shfl_xor_u32(static_cast<uint32_t>(v >> 32), m);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 template <typename K> DEVI K shfl_xor_key(K v, int m);
 template <> DEVI uint32_t shfl_xor_key<uint32_t>(uint32_t v, int m) { return shfl_xor_u32(v, m); }
