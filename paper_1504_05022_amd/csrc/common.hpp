@@ -80,35 +80,69 @@ template <> DEVI uint64_t shfl_key<uint64_t>(uint64_t v, int src) {
   return static_cast<uint64_t>(__shfl(static_cast<long long>(v), src, WAVE));
 }
 
-template <typename K> DEVI K shfl_up_key(K v, int d);
-template <> DEVI uint32_t shfl_up_key<uint32_t>(uint32_t v, int d) {
-  return static_cast<uint32_t>(__shfl_up(static_cast<int>(v), d, WAVE));
+// DPP move of a 32- or 64-bit value: lanes whose source is outside the
+// pattern, and lanes of rows left out by ROWMASK, receive `id`.
+template <int CTRL, int ROWMASK, typename V> DEVI V dpp_move(V x, V id) {
+  static_assert(sizeof(V) == 4 || sizeof(V) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(V) == 4) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, id),
+                                                             __builtin_bit_cast(int, x), CTRL,
+                                                             ROWMASK, 0xF, false));
+  } else {
+    const uint64_t ux = __builtin_bit_cast(uint64_t, x), ui = __builtin_bit_cast(uint64_t, id);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+        static_cast<int>(ui), static_cast<int>(ux), CTRL, ROWMASK, 0xF, false));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+        static_cast<int>(ui >> 32), static_cast<int>(ux >> 32), CTRL, ROWMASK, 0xF, false));
+    return __builtin_bit_cast(V, (static_cast<uint64_t>(hi) << 32) | lo);
+  }
 }
-template <> DEVI uint64_t shfl_up_key<uint64_t>(uint64_t v, int d) {
-  return static_cast<uint64_t>(__shfl_up(static_cast<long long>(v), d, WAVE));
+constexpr int DPP_ROW_SHR = 0x110;      // + n: lane i of a row of 16 reads lane i - n
+constexpr int DPP_WAVE_SHR1 = 0x138;    // lane i reads lane i - 1 of the wavefront
+constexpr int DPP_ROW_BCAST15 = 0x142;  // last lane of each row to the next row
+constexpr int DPP_ROW_BCAST31 = 0x143;  // lane 31 to rows 2 and 3
+
+// Value of lane (lane - 1); lane 0 receives `id`.
+template <typename V> DEVI V wave_shr1(V x, V id) { return dpp_move<DPP_WAVE_SHR1, 0xF>(x, id); }
+
+template <typename K> DEVI K shfl_up_key(K v, int d) {
+  if (d == 1) return wave_shr1<K>(v, K(0));
+  if constexpr (sizeof(K) == 4)
+    return static_cast<K>(__shfl_up(static_cast<int>(v), d, WAVE));
+  else
+    return static_cast<K>(__shfl_up(static_cast<long long>(v), d, WAVE));
 }
 
 // ------------------------------------------------------------- group scans
-// Scans over aligned groups of G consecutive lanes (G a power of two <= 64).
+// Scans over aligned groups of G consecutive lanes (G a power of two <= 64),
+// as DPP shifts inside rows of 16 lanes and broadcasts across rows.
 
-template <int G, typename V> DEVI V group_incl_sum(V x) {
+template <int G, typename V, typename Op> DEVI V group_incl_scan(V x, V id, Op op) {
   const int lg = lane() & (G - 1);
-#pragma unroll
-  for (int o = 1; o < G; o <<= 1) {
-    V y = __shfl_up(x, o, WAVE);
-    if (lg >= o) x += y;
+  if constexpr (G >= 2) {
+    const V y = dpp_move<DPP_ROW_SHR + 1, 0xF>(x, id);
+    x = op(x, (G >= 16 || lg >= 1) ? y : id);
   }
+  if constexpr (G >= 4) {
+    const V y = dpp_move<DPP_ROW_SHR + 2, 0xF>(x, id);
+    x = op(x, (G >= 16 || lg >= 2) ? y : id);
+  }
+  if constexpr (G >= 8) {
+    const V y = dpp_move<DPP_ROW_SHR + 4, 0xF>(x, id);
+    x = op(x, (G >= 16 || lg >= 4) ? y : id);
+  }
+  if constexpr (G >= 16) x = op(x, dpp_move<DPP_ROW_SHR + 8, 0xF>(x, id));
+  if constexpr (G >= 32) x = op(x, dpp_move<DPP_ROW_BCAST15, 0xA>(x, id));
+  if constexpr (G >= 64) x = op(x, dpp_move<DPP_ROW_BCAST31, 0xC>(x, id));
   return x;
 }
 
+template <int G, typename V> DEVI V group_incl_sum(V x) {
+  return group_incl_scan<G, V>(x, V(0), [](V a, V b) { return a + b; });
+}
+
 template <int G> DEVI int group_incl_max(int x) {
-  const int lg = lane() & (G - 1);
-#pragma unroll
-  for (int o = 1; o < G; o <<= 1) {
-    int y = __shfl_up(x, o, WAVE);
-    if (lg >= o) x = max(x, y);
-  }
-  return x;
+  return group_incl_scan<G, int>(x, INT32_MIN, [](int a, int b) { return a > b ? a : b; });
 }
 
 // Value held by the last lane of the group.
@@ -171,7 +205,7 @@ template <int NT> DEVI int block_excl_max(int x, int *smem) {
   const int inc = group_incl_max<WAVE>(x);
   const int w = threadIdx.x / WAVE;
   if (lane() == WAVE - 1) smem[w] = inc;
-  int prev = __shfl_up(inc, 1, WAVE);
+  int prev = wave_shr1(inc, -1);
   if (lane() == 0) prev = -1;
   __syncthreads();
   int before = -1;

@@ -98,7 +98,7 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
     st[kk] = run;
   }
   const int incl = group_incl_max<G>(run);
-  int prev = __shfl_up(incl, 1, WAVE);
+  int prev = wave_shr1(incl, -1);
   if (pos == 0) prev = -1;
 
   // B index and a_ij of every product, resolved in this lane-blocked order

@@ -1621,7 +1621,7 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
     st[kk] = run;
   }
   const int incl = group_incl_max<WAVE>(run);
-  int prev = __shfl_up(incl, 1, WAVE);
+  int prev = wave_shr1(incl, -1);
   if (pos == 0) prev = -1;
   // B index and a_ij of every product, resolved in lane-blocked order and
   // handed over through LDS so that consecutive lanes gather consecutive
@@ -1923,7 +1923,7 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
       sgk[kk] = run;
     }
     const int inc = group_incl_max<WAVE>(run);
-    int prev = __shfl_up(inc, 1, WAVE);
+    int prev = wave_shr1(inc, -1);
     if (pos == 0) prev = -1;
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) {
