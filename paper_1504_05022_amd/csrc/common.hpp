@@ -102,8 +102,12 @@ constexpr int DPP_WAVE_SHR1 = 0x138;    // lane i reads lane i - 1 of the wavefr
 constexpr int DPP_ROW_BCAST15 = 0x142;  // last lane of each row to the next row
 constexpr int DPP_ROW_BCAST31 = 0x143;  // lane 31 to rows 2 and 3
 
+constexpr int DPP_WAVE_SHL1 = 0x130;    // lane i reads lane i + 1 of the wavefront
+
 // Value of lane (lane - 1); lane 0 receives `id`.
 template <typename V> DEVI V wave_shr1(V x, V id) { return dpp_move<DPP_WAVE_SHR1, 0xF>(x, id); }
+// Value of lane (lane + 1); lane 63 receives `id`.
+template <typename V> DEVI V wave_shl1(V x, V id) { return dpp_move<DPP_WAVE_SHL1, 0xF>(x, id); }
 
 template <typename K> DEVI K shfl_up_key(K v, int d) {
   if (d == 1) return wave_shr1<K>(v, K(0));
