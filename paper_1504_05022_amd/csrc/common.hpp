@@ -323,6 +323,80 @@ template <> struct KeyMax<uint64_t> { static constexpr uint64_t v = 0xffffffffff
 template <int B> struct Log2 { static constexpr int v = 1 + Log2<B / 2>::v; };
 template <> struct Log2<1> { static constexpr int v = 0; };
 
+// Folds a tile sorted on (column, stream index) and held by an aligned group
+// of G lanes: rank pos*K + kk (pos = lane in the group) is key[kk], the
+// product of stream index s is pv[s].  Every run of equal
+// columns is summed in rank order from +0.0 -- the sequential sum of
+// Gustavson's method -- in registers; a run that crosses into the next lane
+// continues from that lane's left neighbour's running sum.  The results go,
+// in column order, to the LDS staging arrays sc (column + cbase) and sv,
+// which may overlap the key buffer and pv; returns their number.  Only
+// wavefront-level ordering is used.
+template <typename T, int G, int K, typename Key>
+DEVI int fold_runs(const Key (&key)[K], const int tn, const T *pv, int32_t *sc, T *sv,
+                   const int32_t cbase) {
+  constexpr int U = G * K;
+  constexpr int LOGU = Log2<U>::v;
+  constexpr Key KMAX = KeyMax<Key>::v;
+  const int pos = lane() & (G - 1);
+  const Key pk = shfl_up_key<Key>(key[K - 1], 1);  // rank pos*K - 1
+  const Key nk = wave_shl1<Key>(key[0], KMAX);     // rank pos*K + K
+  uint32_t hmask = 0, tmask = 0;
+  int nt = 0;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int l = pos * K + kk;
+    const Key c = key[kk] >> LOGU;
+    const Key before = kk > 0 ? key[kk - 1] : pk;
+    const Key after = kk + 1 < K ? key[kk + 1] : nk;
+    const bool valid = l < tn;
+    const bool head = valid && (l == 0 || (before >> LOGU) != c);
+    const bool tail = valid && (l + 1 == tn || (after >> LOGU) != c);
+    hmask |= head ? (1u << kk) : 0u;
+    tmask |= tail ? (1u << kk) : 0u;
+    nt += tail ? 1 : 0;
+  }
+  T acc[K];
+  auto chain = [&](const T cin) {
+    T run = cin;
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      const T v = pv[static_cast<int>(key[kk] & (U - 1))];
+      run = (hmask & (1u << kk)) ? T(0) + v : run + v;
+      acc[kk] = run;
+    }
+  };
+  chain(T(0));
+  // lanes whose first rank continues a run wait for the left neighbour's
+  // final running sum (rank 0 always starts a run, so this ends; values
+  // shifted in from another group are never used)
+  bool prefix_ok = !(pos * K < tn && !(hmask & 1u));
+  bool tail_ok = prefix_ok || hmask != 0u;
+  while (__any(!prefix_ok)) {
+    const T cin = wave_shr1<T>(acc[K - 1], T(0));
+    const int left_ok = wave_shr1<int>(tail_ok ? 1 : 0, 1);
+    if (!prefix_ok && left_ok) {
+      chain(cin);
+      prefix_ok = true;
+      tail_ok = true;
+    }
+  }
+  const int incl_t = group_incl_sum<G>(nt);
+  const int r = group_last<G>(incl_t);
+  wave_sync();  // every read of pv is done before the staging overwrites it
+  int o = incl_t - nt;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    if (tmask & (1u << kk)) {
+      sc[o] = cbase + static_cast<int32_t>(key[kk] >> LOGU);
+      sv[o] = acc[kk];
+      ++o;
+    }
+  }
+  wave_sync();
+  return r;
+}
+
 // Values are summed without fused multiply-add (the library is compiled with
 // -ffp-contract=off), products first rounded, then added in sequence order.
 

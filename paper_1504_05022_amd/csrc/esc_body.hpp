@@ -165,44 +165,17 @@ DEVI void esc_rows(const EscArgs<T> &a, const int32_t *rows, const int64_t base,
   }
 
   group_bitonic_sort<G, K, Key>(key);
+  wave_sync();  // every product is in pv
 
-#pragma unroll
-  for (int kk = 0; kk < K; ++kk) sk[kk * G + pos] = key[kk];
-  const Key pk = shfl_up_key<Key>(key[K - 1], 1);
-  wave_sync();
-
-  // compress: count the distinct columns, place them with a group scan,
-  // then fold every column's products in expansion order
-  uint32_t hmask = 0;
-  int nh = 0;
-#pragma unroll
-  for (int kk = 0; kk < K; ++kk) {
-    const int l = pos * K + kk;
-    const Key before = kk > 0 ? key[kk - 1] : pk;
-    const bool head = l < u && (l == 0 || (before >> LOGU) != (key[kk] >> LOGU));
-    hmask |= head ? (1u << kk) : 0u;
-    nh += head ? 1 : 0;
-  }
-  const int incl_h = group_incl_sum<G>(nh);
-  const int total = group_last<G>(incl_h);
+  // compress: fold every column's products in expansion order (registers),
+  // stage the distinct columns in LDS, store them with consecutive lanes
+  int32_t *sc = reinterpret_cast<int32_t *>(sk);
+  const int total = fold_runs<T, G, K, Key>(key, act ? u : 0, pv, sc, pv, 0);
   if (act) {
-    int64_t o = gcto[i] + (incl_h - nh);
-#pragma unroll
-    for (int kk = 0; kk < K; ++kk) {
-      if (hmask & (1u << kk)) {
-        const int l = pos * K + kk;
-        const Key c = key[kk] >> LOGU;
-        T v = T(0);
-        v = v + pv[static_cast<int>(key[kk] & (U - 1))];
-        for (int l2 = l + 1; l2 < u; ++l2) {
-          const Key k2 = sk[ix(l2)];
-          if ((k2 >> LOGU) != c) break;
-          v = v + pv[static_cast<int>(k2 & (U - 1))];
-        }
-        gct_col[o] = static_cast<int32_t>(c);
-        gct_val[o] = v;
-        ++o;
-      }
+    const int64_t o = gcto[i];
+    for (int x = pos; x < total; x += G) {
+      gct_col[o + x] = sc[x];
+      gct_val[o + x] = pv[x];
     }
     if (pos == 0) grownnz[i] = total;
   }

@@ -1566,78 +1566,6 @@ DEVI int wpad(int r) { return r + (r >> 6); }
 // and need every resident wavefront they can get.
 template <int K> constexpr int wave_occupancy() { return K <= 8 ? 5 : 3; }
 
-// Folds a wavefront tile sorted on (column, stream index): rank pos*K + kk
-// is key[kk], the product of stream index s is pv[s].  Every run of equal
-// columns is summed in rank order from +0.0 -- the sequential sum of
-// Gustavson's method -- in registers; a run that crosses into the next lane
-// continues from that lane's left neighbour's running sum.  The results go,
-// in column order, to the LDS staging arrays sc (column + cbase) and sv,
-// which may overlap the key buffer and pv; returns their number.  Only
-// wavefront-level ordering is used.
-template <typename T, int K, typename Key>
-DEVI int fold_runs(const Key (&key)[K], const int tn, const T *pv, int32_t *sc, T *sv,
-                   const int32_t cbase) {
-  constexpr int U = WAVE * K;
-  constexpr int LOGU = Log2<U>::v;
-  constexpr Key KMAX = KeyMax<Key>::v;
-  const int pos = lane();
-  const Key pk = shfl_up_key<Key>(key[K - 1], 1);  // rank pos*K - 1
-  const Key nk = wave_shl1<Key>(key[0], KMAX);     // rank pos*K + K
-  uint32_t hmask = 0, tmask = 0;
-  int nt = 0;
-#pragma unroll
-  for (int kk = 0; kk < K; ++kk) {
-    const int l = pos * K + kk;
-    const Key c = key[kk] >> LOGU;
-    const Key before = kk > 0 ? key[kk - 1] : pk;
-    const Key after = kk + 1 < K ? key[kk + 1] : nk;
-    const bool valid = l < tn;
-    const bool head = valid && (l == 0 || (before >> LOGU) != c);
-    const bool tail = valid && (l + 1 == tn || (after >> LOGU) != c);
-    hmask |= head ? (1u << kk) : 0u;
-    tmask |= tail ? (1u << kk) : 0u;
-    nt += tail ? 1 : 0;
-  }
-  T acc[K];
-  auto chain = [&](const T cin) {
-    T run = cin;
-#pragma unroll
-    for (int kk = 0; kk < K; ++kk) {
-      const T v = pv[static_cast<int>(key[kk] & (U - 1))];
-      run = (hmask & (1u << kk)) ? T(0) + v : run + v;
-      acc[kk] = run;
-    }
-  };
-  chain(T(0));
-  // lanes whose first rank continues a run wait for the left neighbour's
-  // final running sum (rank 0 always starts a run, so this ends)
-  bool prefix_ok = !(pos * K < tn && !(hmask & 1u));
-  bool tail_ok = prefix_ok || hmask != 0u;
-  while (__any(!prefix_ok)) {
-    const T cin = wave_shr1<T>(acc[K - 1], T(0));
-    const int left_ok = wave_shr1<int>(tail_ok ? 1 : 0, 1);
-    if (!prefix_ok && left_ok) {
-      chain(cin);
-      prefix_ok = true;
-      tail_ok = true;
-    }
-  }
-  const int incl_t = group_incl_sum<WAVE>(nt);
-  const int r = group_last<WAVE>(incl_t);
-  wave_sync();  // every read of pv is done before the staging overwrites it
-  int o = incl_t - nt;
-#pragma unroll
-  for (int kk = 0; kk < K; ++kk) {
-    if (tmask & (1u << kk)) {
-      sc[o] = cbase + static_cast<int32_t>(key[kk] >> LOGU);
-      sv[o] = acc[kk];
-      ++o;
-    }
-  }
-  wave_sync();
-  return r;
-}
-
 template <typename T, int K, typename Key>
 DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
                     unsigned char *lds_a, T *lds_b) {
@@ -1822,7 +1750,7 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
 
   // one-item row: fold every column in position order into the row's place
   int32_t *sc = reinterpret_cast<int32_t *>(lds_a);
-  const int r = fold_runs<T, K, Key>(key, tn, pv, sc, lds_b, 0);
+  const int r = fold_runs<T, WAVE, K, Key>(key, tn, pv, sc, lds_b, 0);
   int32_t *dcol = a.pcol + lr.pbase;
   T *dval = a.pval + lr.pbase;
   for (int x = pos; x < r; x += WAVE) {
@@ -2015,7 +1943,7 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
   wave_sync();  // gi is dead from here on
   int32_t *sc = reinterpret_cast<int32_t *>(lds_a);
   T *sv = lds_b;
-  const int r = fold_runs<T, K, Key>(key, tn, pv, sc, sv, c0);
+  const int r = fold_runs<T, WAVE, K, Key>(key, tn, pv, sc, sv, c0);
   int32_t *dcol = a.ocol + lr.pbase + obase;
   T *dval = a.oval + lr.pbase + obase;
   for (int x = pos; x < r; x += WAVE) {
