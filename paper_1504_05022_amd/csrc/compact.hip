@@ -3,7 +3,7 @@
 // the temporary matrix C~ into C.  A wavefront takes 32 consecutive short
 // rows and streams all their entries at once, so the copy is coalesced and
 // no wavefront waits on one row's metadata; long rows are copied piece by
-// piece by whole work-groups.
+// piece, one wavefront each.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -118,19 +118,42 @@ __global__ __launch_bounds__(CP_NT) void k_compact_rows(CompactArgs<T> a, int64_
                                tabs[threadIdx.x / WAVE]);
 }
 
-// Long rows, piece by piece: one work-group per piece (pieces hold a few
-// hundred to a few thousand entries).
+// Long rows, piece by piece: one wavefront per piece (pieces hold a few
+// hundred entries), loads of up to CP_PIECE_BATCH passes issued before
+// their stores.
+constexpr int CP_PIECE_BATCH = 8;
+
 template <typename T>
-__global__ __launch_bounds__(CP_NT) void k_compact_pieces(CompactArgs<T> a) {
-  const Piece pc = a.pieces[blockIdx.x];
+__global__ __launch_bounds__(CP_NT) void k_compact_pieces(CompactArgs<T> a, int64_t npieces) {
+  const int64_t pid = (static_cast<int64_t>(blockIdx.x) * CP_NT + threadIdx.x) / WAVE;
+  if (pid >= npieces) return;  // uniform across the wavefront
+  const Piece pc = a.pieces[pid];
   if (pc.cnt <= 0) return;
   const LongRow lr = a.lrows[pc.lrow];
-  const int64_t dst = a.rowoff[lr.row] + a.pscan[blockIdx.x] - a.pscan[lr.piece0];
+  const int64_t dst = a.rowoff[lr.row] + a.pscan[pid] - a.pscan[lr.piece0];
   const GLOBAL_AS int32_t *sc = as_global(pc.col);
   const GLOBAL_AS T *sv = as_global(reinterpret_cast<const T *>(pc.val));
-  for (int64_t x = threadIdx.x; x < pc.cnt; x += CP_NT) {
-    a.c_col[dst + x] = sc[x];
-    a.c_val[dst + x] = sv[x];
+  GLOBAL_AS int32_t *dc = as_global_mut(a.c_col + dst);
+  GLOBAL_AS T *dv = as_global_mut(a.c_val + dst);
+  const int64_t n = pc.cnt;
+  for (int64_t x0 = 0; x0 < n; x0 += CP_PIECE_BATCH * WAVE) {
+    int32_t c[CP_PIECE_BATCH];
+    T v[CP_PIECE_BATCH];
+#pragma unroll
+    for (int b = 0; b < CP_PIECE_BATCH; ++b) {
+      const int64_t x = x0 + b * WAVE + lane();
+      const int64_t xc = x < n ? x : n - 1;
+      c[b] = sc[xc];
+      v[b] = sv[xc];
+    }
+#pragma unroll
+    for (int b = 0; b < CP_PIECE_BATCH; ++b) {
+      const int64_t x = x0 + b * WAVE + lane();
+      if (x < n) {
+        dc[x] = c[b];
+        dv[x] = v[b];
+      }
+    }
   }
 }
 
@@ -141,7 +164,8 @@ void launch_compact(const CompactArgs<T> &a, int64_t m, int64_t npieces, hipStre
   hipLaunchKernelGGL((k_compact_rows<T>), dim3((rwaves * WAVE + CP_NT - 1) / CP_NT), dim3(CP_NT),
                      0, s, a, m);
   if (npieces > 0)
-    hipLaunchKernelGGL((k_compact_pieces<T>), dim3(npieces), dim3(CP_NT), 0, s, a);
+    hipLaunchKernelGGL((k_compact_pieces<T>), dim3((npieces * WAVE + CP_NT - 1) / CP_NT),
+                       dim3(CP_NT), 0, s, a, npieces);
 }
 
 template void launch_compact<float>(const CompactArgs<float> &, int64_t, int64_t, hipStream_t);

@@ -1713,19 +1713,30 @@ DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
     int32_t *ptab = a.split + lr.sbase;
     int32_t *dcol = a.pcol + lr.pbase + p0;
     T *dval = a.pval + lr.pbase + p0;
-    // rank r = kk * 64 + lane: consecutive lanes write consecutive entries
+    // rank r = kk * 64 + lane: consecutive lanes write consecutive entries;
+    // every LDS read is issued before the stores
+    Key krs[K];
+    T vrs[K];
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      const int r = kk * WAVE + pos;
+      const Key kv = sk[wpad(r)];
+      krs[kk] = r < tn ? kv : KMAX;
+    }
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) vrs[kk] = pv[static_cast<int>(krs[kk] & (U - 1))];
     Key carry = 0;  // key of the rank before this pass's first
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) {
       const int r = kk * WAVE + pos;
-      const Key kr = r < tn ? sk[wpad(r)] : KMAX;
+      const Key kr = krs[kk];
       Key before = shfl_up_key<Key>(kr, 1);
       if (pos == 0) before = carry;
       carry = shfl_key<Key>(kr, WAVE - 1);
       if (r < tn) {
         const int32_t c = static_cast<int32_t>(kr >> LOGU);
         dcol[r] = c;
-        dval[r] = pv[static_cast<int>(kr & (U - 1))];
+        dval[r] = vrs[kk];
         const int32_t q = c >> shift;
         const int32_t qp = r > 0 ? (static_cast<int32_t>(before >> LOGU) >> shift) : -1;
         for (int32_t qq = qp + 1; qq <= q && qq < np; ++qq)
