@@ -356,40 +356,55 @@ DEVI int fold_runs(const Key (&key)[K], const int tn, const T *pv, int32_t *sc, 
     tmask |= tail ? (1u << kk) : 0u;
     nt += tail ? 1 : 0;
   }
-  T acc[K];
-  auto chain = [&](const T cin) {
+  // running sum over this lane's ranks, restarting at every head, from cin
+  auto run_from = [&](T run) {
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      const T v = pv[static_cast<int>(key[kk] & (U - 1))];
+      run = (hmask & (1u << kk)) ? T(0) + v : run + v;
+    }
+    return run;
+  };
+  // a lane whose first rank continues a run starts from the left
+  // neighbour's final running sum: that is final once the neighbour has a
+  // head of its own or has received its start (rank 0 always starts a run,
+  // so this ends; values shifted in from another group are never used)
+  const bool cont0 = pos * K < tn && !(hmask & 1u);
+  T last = run_from(T(0));
+  T cin = T(0);
+  bool have = !cont0;
+  bool last_ok = have || hmask != 0u;
+  while (__any(!have)) {
+    const T left = wave_shr1<T>(last, T(0));
+    const int left_ok = wave_shr1<int>(last_ok ? 1 : 0, 1);
+    if (!have && left_ok) {
+      cin = left;
+      last = run_from(cin);
+      have = true;
+      last_ok = true;
+    }
+  }
+  const int incl_t = group_incl_sum<G>(nt);
+  const int r = group_last<G>(incl_t);
+  // final pass: tails take their run's sum (all pv reads precede the
+  // staging writes, which may overwrite pv)
+  T tv[K];
+  {
     T run = cin;
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) {
       const T v = pv[static_cast<int>(key[kk] & (U - 1))];
       run = (hmask & (1u << kk)) ? T(0) + v : run + v;
-      acc[kk] = run;
-    }
-  };
-  chain(T(0));
-  // lanes whose first rank continues a run wait for the left neighbour's
-  // final running sum (rank 0 always starts a run, so this ends; values
-  // shifted in from another group are never used)
-  bool prefix_ok = !(pos * K < tn && !(hmask & 1u));
-  bool tail_ok = prefix_ok || hmask != 0u;
-  while (__any(!prefix_ok)) {
-    const T cin = wave_shr1<T>(acc[K - 1], T(0));
-    const int left_ok = wave_shr1<int>(tail_ok ? 1 : 0, 1);
-    if (!prefix_ok && left_ok) {
-      chain(cin);
-      prefix_ok = true;
-      tail_ok = true;
+      tv[kk] = run;
     }
   }
-  const int incl_t = group_incl_sum<G>(nt);
-  const int r = group_last<G>(incl_t);
-  wave_sync();  // every read of pv is done before the staging overwrites it
+  wave_sync();
   int o = incl_t - nt;
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     if (tmask & (1u << kk)) {
       sc[o] = cbase + static_cast<int32_t>(key[kk] >> LOGU);
-      sv[o] = acc[kk];
+      sv[o] = tv[kk];
       ++o;
     }
   }
