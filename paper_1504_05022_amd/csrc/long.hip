@@ -1564,7 +1564,7 @@ DEVI int wpad(int r) { return r + (r >> 6); }
 // Wavefronts per SIMD that the tile's LDS allows (FP64 values): the register
 // budget of the wavefront kernels is held to it, since they wait on memory
 // and need every resident wavefront they can get.
-template <int K> constexpr int wave_occupancy() { return K <= 8 ? 5 : 3; }
+template <int K> constexpr int wave_occupancy() { return K <= 8 ? 6 : 3; }
 
 template <typename T, int K, typename Key>
 DEVI void wave_item(LongArgs<T> &a, const int32_t item_id, const LongItem &item,
@@ -1797,7 +1797,8 @@ void k_long_w(LongArgs<T> a, int64_t nitems,
   constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
   __shared__ __align__(16) unsigned char s_a[NWV][(U + U / WAVE) * KB];
   __shared__ __align__(16) T s_b[NWV][U];
-  const int w = threadIdx.x / WAVE;
+  // wave-uniform (so item and row records are read through the scalar cache)
+  const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / WAVE));
   const int64_t id0 = xcd_block_id<16>() * NWV + w;
   const int64_t n = in_list ? static_cast<int64_t>(*in_cnt) : nitems;
   const int64_t stride = in_list ? static_cast<int64_t>(gridDim.x) * NWV : n;
@@ -1989,7 +1990,8 @@ void k_combine_w(LongArgs<T> a, int64_t npieces,
   constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
   __shared__ __align__(16) unsigned char s_a[NWV][U * KB];
   __shared__ __align__(16) T s_b[NWV][U];
-  const int w = threadIdx.x / WAVE;
+  // wave-uniform (so piece and row records are read through the scalar cache)
+  const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / WAVE));
   const int64_t id = static_cast<int64_t>(blockIdx.x) * NWV + w;
   if (in_list == nullptr) {
     if (id >= npieces) return;  // uniform across the wavefront; no work-group barriers here
