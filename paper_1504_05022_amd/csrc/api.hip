@@ -733,6 +733,15 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   stage_begin(p, SPGEMM_T_SCAN, s);
   scan_i64(p->rownnz, m, p->rowoff, p->part, s);
   stage_end(p, SPGEMM_T_SCAN, s);
+  // C's row pointers have a known size: allocated while the GPU is busy,
+  // released again if anything below fails
+  struct OwnedBuf {
+    const Allocator &al;
+    hipStream_t s;
+    void *p;
+    ~OwnedBuf() { al.put(p, s); }
+  } crp_guard{p->al, s, p->al.get(static_cast<size_t>(m + 1) * 4, s)};
+  if (!crp_guard.p) return fail(SPGEMM_ENOMEM, "allocation of C failed");
   {
     unsigned int *f2 = fail2_a, *f2_other = fail2_b;
     unsigned int *fl = fail_a, *fl_other = fail_b;
@@ -783,11 +792,10 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     I.bytes_scratch += static_cast<int64_t>(pool_chunk_bytes(e, sizeof(T)));
 
   // ---- stage 4b: allocate C and copy C~ into it
-  void *crp = p->al.get(static_cast<size_t>(m + 1) * 4, s);
-  void *ccol = crp ? p->al.get(static_cast<size_t>(nnz) * 4, s) : nullptr;
+  void *crp = crp_guard.p;
+  void *ccol = p->al.get(static_cast<size_t>(nnz) * 4, s);
   void *cval = ccol ? p->al.get(static_cast<size_t>(nnz) * sizeof(T), s) : nullptr;
   if (!cval) {
-    p->al.put(crp, s);
     p->al.put(ccol, s);
     return fail(SPGEMM_ENOMEM, "allocation of C failed");
   }
@@ -812,11 +820,11 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   stage_end(p, SPGEMM_T_COPY, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
-    p->al.put(crp, s);
     p->al.put(ccol, s);
     p->al.put(cval, s);
     return hip_fail(e, "compute");
   }
+  crp_guard.p = nullptr;  // C's arrays belong to the caller from here on
   C->rows = m;
   C->cols = p->n;
   C->nnz = nnz;
