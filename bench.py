@@ -118,9 +118,11 @@ def wave_kernel_bytes(A, B, crp, cci, s):
     row pointer: 16 + s bytes each), the gathered B entries (4 + s each) and
     the segment's products plus its range starts, which it writes.
     Range kernel (its first pass, 512-entry wavefront sorts), per column
-    range of a split row: the range starts and partial records of every
-    segment (32 bytes each), its entries (4 + s each, only if it holds at
-    most 512 of them; larger ranges go on to the next pass) and its result."""
+    range of a split row: its entries (4 + s each, only if it holds at most
+    512 of them; larger ranges go on to the next pass), its result and piece
+    record; per split row, the range-start table once (4 bytes per range
+    boundary and segment: a range reads the row of its own start and of the
+    next range's start, so each row is counted once)."""
     arp = A.row_ptr.astype(np.int64)
     brp = B.row_ptr.astype(np.int64)
     deg = np.diff(arp)
@@ -156,7 +158,7 @@ def wave_kernel_bytes(A, B, crp, cci, s):
         E = np.bincount(cols >> shift, minlength=npiece)
         r = np.bincount(cci[int(crp[i]):int(crp[i + 1])] >> shift, minlength=npiece)
         small = E <= WAVE_TILE // 2  # the first (512-entry) wavefront pass
-        rng_bytes += npiece * nseg * 32 + int((E[small] + r[small]).sum()) * (4 + s) + npiece * 64
+        rng_bytes += (npiece + 1) * nseg * 4 + int((E[small] + r[small]).sum()) * (4 + s) + npiece * 64
     return seg_bytes, rng_bytes
 
 
