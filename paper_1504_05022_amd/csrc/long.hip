@@ -1990,9 +1990,11 @@ void k_combine_w(LongArgs<T> a, int64_t npieces,
   constexpr int KB = sizeof(Key) > 4 ? static_cast<int>(sizeof(Key)) : 4;
   __shared__ __align__(16) unsigned char s_a[NWV][U * KB];
   __shared__ __align__(16) T s_b[NWV][U];
-  // wave-uniform (so piece and row records are read through the scalar cache)
+  // wave-uniform (so piece and row records are read through the scalar cache);
+  // runs of 4 work-groups (16 neighbouring ranges, which read neighbouring
+  // entries of every segment) share an XCD
   const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / WAVE));
-  const int64_t id = static_cast<int64_t>(blockIdx.x) * NWV + w;
+  const int64_t id = xcd_block_id<4>() * NWV + w;
   if (in_list == nullptr) {
     if (id >= npieces) return;  // uniform across the wavefront; no work-group barriers here
     wave_piece<T, K, Key, MAXS>(a, static_cast<int32_t>(id), s_a[w], s_b[w], out_list, out_cnt);
