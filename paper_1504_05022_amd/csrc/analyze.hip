@@ -74,13 +74,24 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_part(int64_t *part, int64_t nb
 // spread over the banks).
 DEVI int scan_lds_ix(int i) { return i + i / SCAN_IPT; }
 
-template <typename F>
+// SELF: `part` holds the raw tile sums and every work-group adds up those
+// of the tiles before it (fine for a few thousand tiles; saves the launch of
+// phase 2); otherwise `part` is phase 2's exclusive scan.
+template <typename F, bool SELF>
 __global__ __launch_bounds__(SCAN_NT) void k_scan_down(F f, int64_t n, const int64_t *part,
                                                        int64_t nb, int64_t *out) {
   __shared__ int64_t sm[SCAN_NT / WAVE + 1];
   __shared__ int64_t tile[SCAN_TILE + SCAN_TILE / SCAN_IPT];
   const int t = threadIdx.x;
   const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE;
+  int64_t offset = 0;
+  if constexpr (SELF) {
+    int64_t ps = 0;
+    for (int64_t b = t; b < static_cast<int64_t>(blockIdx.x); b += SCAN_NT) ps += part[b];
+    block_excl_sum<SCAN_NT>(ps, sm, offset);
+  } else {
+    offset = part[blockIdx.x];
+  }
 #pragma unroll
   for (int j = 0; j < SCAN_IPT; ++j) {
     const int i = j * SCAN_NT + t;
@@ -96,7 +107,7 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_down(F f, int64_t n, const int
     s += v[j];
   }
   int64_t tot;
-  int64_t ex = block_excl_sum<SCAN_NT>(s, sm, tot) + part[blockIdx.x];
+  int64_t ex = block_excl_sum<SCAN_NT>(s, sm, tot) + offset;
 #pragma unroll
   for (int j = 0; j < SCAN_IPT; ++j) {
     tile[scan_lds_ix(t * SCAN_IPT + j)] = ex;  // the slots this thread read
@@ -109,8 +120,15 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_down(F f, int64_t n, const int
     const int64_t e = base + i;
     if (e < n) out[e] = tile[scan_lds_ix(i)];
   }
-  if (blockIdx.x == 0 && t == 0) out[n] = part[nb];
+  if constexpr (SELF) {
+    if (blockIdx.x == nb - 1 && t == 0) out[n] = offset + tot;
+  } else {
+    if (blockIdx.x == 0 && t == 0) out[n] = part[nb];
+  }
 }
+
+// tiles up to which a work-group of phase 3 sums the earlier tile sums itself
+constexpr int64_t SCAN_SELF_MAX_TILES = 4096;
 
 template <typename F>
 static void scan_with(F f, int64_t n, int64_t *out, int64_t *part, hipStream_t s) {
@@ -118,13 +136,19 @@ static void scan_with(F f, int64_t n, int64_t *out, int64_t *part, hipStream_t s
   if (nb == 0) {
     // out[0] = 0
     hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(SCAN_NT), 0, s, part, int64_t(0));
-    hipLaunchKernelGGL((k_scan_down<F>), dim3(1), dim3(SCAN_NT), 0, s, f, n, part,
+    hipLaunchKernelGGL((k_scan_down<F, false>), dim3(1), dim3(SCAN_NT), 0, s, f, n, part,
                        int64_t(0), out);
     return;
   }
   hipLaunchKernelGGL((k_scan_reduce<F>), dim3(nb), dim3(SCAN_NT), 0, s, f, n, part);
+  if (nb <= SCAN_SELF_MAX_TILES) {
+    hipLaunchKernelGGL((k_scan_down<F, true>), dim3(nb), dim3(SCAN_NT), 0, s, f, n, part, nb,
+                       out);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(SCAN_NT), 0, s, part, nb);
-  hipLaunchKernelGGL((k_scan_down<F>), dim3(nb), dim3(SCAN_NT), 0, s, f, n, part, nb, out);
+  hipLaunchKernelGGL((k_scan_down<F, false>), dim3(nb), dim3(SCAN_NT), 0, s, f, n, part, nb,
+                     out);
 }
 
 void scan_row_lengths(const int32_t *acol, const int32_t *brp, int64_t n, int64_t *out,
