@@ -681,8 +681,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     if ((rc = new_pool(pool_entries, 0)) != SPGEMM_OK) return rc;
     launch_long_table(p->binlist, S.bin_off[LONG_BIN], nlong, p->u, p->n, p->lp, lrows, nitems,
                       items, states, partials, npieces, piece_lrow, A->row_ptr, p->P, lt_tmp, s);
-    launch_cstate_init(cstates, npieces, s);
-    launch_zero(lcnt, sizeof(LongCounters), s);
+    launch_cstate_init(cstates, npieces, lcnt, s);
     // phase 1: every segment; one wavefront, else one work-group tile, else
     // the level-1 merge method
     stage_begin(p, SPGEMM_T_LONG, s);
@@ -762,8 +761,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
         std::swap(fl, fl_other);
         la.work = nullptr;
         la.fail_list = fl;
-        launch_cstate_init(cstates, npieces, s);
-        launch_zero(lcnt, sizeof(LongCounters), s);
+        launch_cstate_init(cstates, npieces, lcnt, s);
         la.fail_list2 = f2;
         if (S.n_split > 0) {  // some row was split
           launch_combine_wave<T>(la, npieces, s);

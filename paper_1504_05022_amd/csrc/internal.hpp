@@ -294,7 +294,7 @@ void launch_long_table(const int32_t *binlist, int64_t off, int64_t nlong, const
                        LongItem *items, LongState *state, Seq *partials, int64_t npieces,
                        int32_t *piece_lrow, const int32_t *arp, const int64_t *P, int64_t *tmp,
                        hipStream_t s);
-void launch_cstate_init(LongState *state, int64_t n, hipStream_t s);
+void launch_cstate_init(LongState *state, int64_t n, LongCounters *cnt, hipStream_t s);
 int combine_maxs();
 int combine_l1cap();
 constexpr int kLongTile = 1024;

@@ -2066,19 +2066,34 @@ __global__ void k_lt_scan(int64_t *tmp, int64_t nb) {
   }
 }
 
+// SELF: tmp holds the raw block sums and every work-group adds up those of
+// the blocks before it (few blocks; saves the launch of k_lt_scan).
+template <bool SELF>
 __global__ __launch_bounds__(256) void k_lt_write(const int32_t *binlist, int64_t off,
                                                   int64_t nlong, const int64_t *u, int64_t ncols,
                                                   LongParams lp, const int64_t *tmp,
                                                   LongRow *lrows) {
   __shared__ int64_t sm[256 / WAVE + 1];
   const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  int64_t base[4];
+  if constexpr (SELF) {
+    int64_t ps[4] = {0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < static_cast<int64_t>(blockIdx.x); b += 256)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ps[c] += tmp[4 * b + c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) block_excl_sum<256>(ps[c], sm, base[c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) base[c] = tmp[4 * blockIdx.x + c];
+  }
   LongRow lr;
   const LtSums z = lt_plan(binlist, off, t, nlong, u, ncols, lp, lr);
   int64_t tot;
-  const int64_t i0 = block_excl_sum<256>(z.items, sm, tot) + tmp[4 * blockIdx.x + 0];
-  const int64_t p0 = block_excl_sum<256>(z.pieces, sm, tot) + tmp[4 * blockIdx.x + 1];
-  const int64_t u0 = block_excl_sum<256>(z.umulti, sm, tot) + tmp[4 * blockIdx.x + 2];
-  const int64_t s0 = block_excl_sum<256>(z.split, sm, tot) + tmp[4 * blockIdx.x + 3];
+  const int64_t i0 = block_excl_sum<256>(z.items, sm, tot) + base[0];
+  const int64_t p0 = block_excl_sum<256>(z.pieces, sm, tot) + base[1];
+  const int64_t u0 = block_excl_sum<256>(z.umulti, sm, tot) + base[2];
+  const int64_t s0 = block_excl_sum<256>(z.split, sm, tot) + base[3];
   if (t >= nlong) return;
   lr.item0 = i0;
   lr.piece0 = p0;
@@ -2168,9 +2183,14 @@ void launch_long_table(const int32_t *binlist, int64_t off, int64_t nlong, const
   const int64_t nb = (nlong + 255) / 256;
   hipLaunchKernelGGL(k_lt_reduce, dim3(nb), dim3(256), 0, s, binlist, off, nlong, u, ncols, lp,
                      tmp);
-  hipLaunchKernelGGL(k_lt_scan, dim3(1), dim3(64), 0, s, tmp, nb);
-  hipLaunchKernelGGL(k_lt_write, dim3(nb), dim3(256), 0, s, binlist, off, nlong, u, ncols, lp,
-                     tmp, lrows);
+  if (nb <= 1024) {
+    hipLaunchKernelGGL(k_lt_write<true>, dim3(nb), dim3(256), 0, s, binlist, off, nlong, u,
+                       ncols, lp, tmp, lrows);
+  } else {
+    hipLaunchKernelGGL(k_lt_scan, dim3(1), dim3(64), 0, s, tmp, nb);
+    hipLaunchKernelGGL(k_lt_write<false>, dim3(nb), dim3(256), 0, s, binlist, off, nlong, u,
+                       ncols, lp, tmp, lrows);
+  }
   if (nitems > 0)
     hipLaunchKernelGGL(k_lt_items, dim3((nitems + 255) / 256), dim3(256), 0, s, lrows, nlong,
                        nitems, arp, P, items, state, partials);
@@ -2179,9 +2199,11 @@ void launch_long_table(const int32_t *binlist, int64_t off, int64_t nlong, const
                        npieces, piece_lrow);
 }
 
-// Checkpoints of the combine pieces: start of the stream, empty G.
-__global__ void k_cstate_init(LongState *state, int64_t n) {
+// Checkpoints of the combine pieces: start of the stream, empty G; and the
+// work-list counters cleared in the same launch.
+__global__ void k_cstate_init(LongState *state, int64_t n, unsigned int *cnt, int ncnt) {
   const int64_t x = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (x < ncnt) cnt[x] = 0u;
   if (x >= n) return;
   LongState s;
   s.pos = 0;
@@ -2197,9 +2219,12 @@ __global__ void k_cstate_init(LongState *state, int64_t n) {
   state[x] = s;
 }
 
-void launch_cstate_init(LongState *state, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_cstate_init, dim3((n + 255) / 256), dim3(256), 0, s, state, n);
+void launch_cstate_init(LongState *state, int64_t n, LongCounters *cnt, hipStream_t s) {
+  constexpr int ncnt = static_cast<int>(sizeof(LongCounters) / sizeof(unsigned int));
+  static_assert(ncnt <= 256, "counters are cleared by the first work-group");
+  const int64_t nb = n > 0 ? (n + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_cstate_init, dim3(nb), dim3(256), 0, s, state, n,
+                     reinterpret_cast<unsigned int *>(cnt), ncnt);
 }
 
 // rownnz of long rows = sum of their pieces (from the exclusive piece scan)
