@@ -424,11 +424,7 @@ def main():
     wave_mask = (1 << L.STAGES.index("long_wave")) | (1 << L.STAGES.index("combine_wave"))
 
     def step(mask=wave_mask):
-        plan = L.Plan(dA, dA, timing=1, timing_mask=mask)
-        C = plan.compute()
-        info = plan.info
-        plan.close()
-        return C, info
+        return L.spgemm(dA, dA, return_info=True, timing=1, timing_mask=mask)
 
     for _ in range(args.warmup):
         C, info = step()

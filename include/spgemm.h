@@ -211,6 +211,17 @@ int spgemm_plan_info(spgemm_plan plan, spgemm_info *info);
 /* Release the plan and its scratch (ordered on the plan's last stream). */
 int spgemm_plan_destroy(spgemm_plan plan);
 
+/*
+ * C = A*B in one call (stages 1-4 of Section 3.1): spgemm_analyze, then
+ * spgemm_compute, then spgemm_plan_destroy, without returning to the caller
+ * in between.  Arguments, outputs, ownership and synchronisation as for those
+ * three calls; `opt` and `info` may be NULL.  On failure no plan survives and
+ * C is untouched.
+ */
+int spgemm_multiply(const spgemm_csr *A, const spgemm_csr *B, const spgemm_options *opt,
+                    spgemm_alloc_fn alloc_fn, spgemm_free_fn free_fn, void *ctx, void *stream,
+                    spgemm_csr_out *C, spgemm_info *info);
+
 /* ------------------------------------------------------------------------
  * Batched products (extension beyond the paper): many independent
  * C_p = A_p * B_p of uneven sizes and mixed binary32/binary64 values,

@@ -887,6 +887,19 @@ extern "C" int spgemm_plan_destroy(spgemm_plan plan) {
   return SPGEMM_OK;
 }
 
+extern "C" int spgemm_multiply(const spgemm_csr *A, const spgemm_csr *B,
+                               const spgemm_options *opt, spgemm_alloc_fn alloc_fn,
+                               spgemm_free_fn free_fn, void *ctx, void *stream, spgemm_csr_out *C,
+                               spgemm_info *info) {
+  if (!C) return fail(SPGEMM_EINVAL, "C is NULL");
+  spgemm_plan plan = nullptr;
+  int rc = spgemm_analyze(A, B, opt, alloc_fn, free_fn, ctx, stream, &plan, nullptr);
+  if (rc != SPGEMM_OK) return rc;
+  rc = spgemm_compute(plan, A, B, C, stream, info);
+  spgemm_plan_destroy(plan);
+  return rc;
+}
+
 namespace {
 
 // A's transposed pattern (rows of every column, ascending), built once per plan.

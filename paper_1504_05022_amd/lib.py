@@ -85,7 +85,7 @@ class BatchStats(ctypes.Structure):
 EXPORTS = ("spgemm_default_options", "spgemm_strerror", "spgemm_last_error", "spgemm_analyze",
            "spgemm_compute", "spgemm_backward", "spgemm_plan_info", "spgemm_plan_destroy",
            "spgemm_batch_create", "spgemm_batch_run", "spgemm_batch_stats_get",
-           "spgemm_batch_destroy", "spgemm_merge_pairs")
+           "spgemm_batch_destroy", "spgemm_merge_pairs", "spgemm_multiply")
 
 _ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -156,6 +156,10 @@ def load(path: str = LIB_PATH):
     lib.spgemm_merge_pairs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_int, P, P, P, P, P]
     lib.spgemm_merge_pairs.restype = ctypes.c_int
+    lib.spgemm_multiply.argtypes = [ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc),
+                                    ctypes.POINTER(Options), _ALLOC_T, _FREE_T, P, P,
+                                    ctypes.POINTER(CsrOut), ctypes.POINTER(Info)]
+    lib.spgemm_multiply.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -269,12 +273,7 @@ class Plan:
                                  ctypes.byref(out), _stream_handle(), ctypes.byref(info))
         _check(rc)
         self.info = info
-        m, nnz = int(out.rows), int(out.nnz)
-        vt = torch.float64 if out.dtype == F64 else torch.float32
-        rp = _take(out.row_ptr, 4 * (m + 1), torch.int32)
-        ci = _take(out.col_idx, 4 * nnz, torch.int32)
-        va = _take(out.val, vt.itemsize * nnz, vt)
-        return CsrMatrix((m, int(out.cols)), rp, ci, va)
+        return _out_matrix(out)
 
     def backward(self, C: CsrMatrix, dC: torch.Tensor, want_a=True, want_b=True):
         """(dA, dB) value tensors on A's and B's patterns (None where not wanted)."""
@@ -305,14 +304,27 @@ class Plan:
             pass
 
 
+def _out_matrix(out: CsrOut) -> CsrMatrix:
+    """Tensors over the three arrays the library allocated for C."""
+    m, nnz = int(out.rows), int(out.nnz)
+    vt = torch.float64 if out.dtype == F64 else torch.float32
+    rp = _take(out.row_ptr, 4 * (m + 1), torch.int32)
+    ci = _take(out.col_idx, 4 * nnz, torch.int32)
+    va = _take(out.val, vt.itemsize * nnz, vt)
+    return CsrMatrix((m, int(out.cols)), rp, ci, va)
+
+
 def spgemm(A: CsrMatrix, B: CsrMatrix, return_info=False, **kw):
-    """C = A*B (analyze + compute)."""
-    plan = Plan(A, B, **kw)
-    try:
-        C = plan.compute()
-        info = plan.info
-    finally:
-        plan.close()
+    """C = A*B (analyze + compute + release in one library call)."""
+    lib = load()
+    da, db = A.desc(), B.desc()
+    opts = default_options(**kw)
+    out = CsrOut()
+    info = Info()
+    _check(lib.spgemm_multiply(ctypes.byref(da), ctypes.byref(db), ctypes.byref(opts), _alloc_cb,
+                               _free_cb, None, _stream_handle(), ctypes.byref(out),
+                               ctypes.byref(info)))
+    C = _out_matrix(out)
     return (C, info) if return_info else C
 
 

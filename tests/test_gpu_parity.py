@@ -259,6 +259,22 @@ def test_never_split_with_tiny_pool():
     assert np.array_equal(ci0, ci1) and np.array_equal(v0, v1)
 
 
+def test_one_call_multiply_matches_plan():
+    """spgemm_multiply (analyze, compute and release in one call) gives the
+    plan path's C bit for bit, and its info."""
+    import torch
+    from paper_1504_05022_amd import lib as L
+    A, _ = S.config2(n=8000, cap=300)
+    (rp, ci, v), info = check(A, A)
+    dA = L.CsrMatrix.from_host(A)
+    C, i2 = L.spgemm(dA, dA, return_info=True)
+    torch.cuda.synchronize()
+    _, _, rp2, ci2, v2 = C.to_host()
+    assert np.array_equal(rp, rp2) and np.array_equal(ci, ci2) and np.array_equal(v, v2)
+    assert i2.nnz_c == info.nnz_c and i2.flops == info.flops
+    assert list(i2.bin_count) == list(info.bin_count)
+
+
 def test_options_do_not_change_result():
     # same product segments throughout (seg fixed), so even split rows are
     # summed identically
