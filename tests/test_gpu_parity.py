@@ -169,6 +169,16 @@ def test_config4_sample():
         check(A, B)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_wide_column_space(dtype):
+    """2^27 columns: the sort keys of the short-row kernels, of the long-row
+    segments and of the column ranges of rows with up to about 2000 products
+    need more than 32 bits (the 64-bit key variants of every kernel)."""
+    A = S.powerlaw_csr(3000, 2.1, 16.0, 600, workload=11, dtype=dtype)
+    B = S.uniform_csr(3000, 1 << 27, 24, workload=11, sub=1, dtype=dtype)
+    check(A, B)
+
+
 def test_degenerate_shapes():
     from tests.helpers import random_csr
     rng = np.random.default_rng(5)
