@@ -303,6 +303,10 @@ extern "C" int spgemm_merge_pairs(int algorithm, int value_bytes, int64_t l, int
     return SPGEMM_EOVERFLOW;
   }
   const int64_t tile = 2 * l > 2 * threads ? 2 * l : 2 * static_cast<int64_t>(threads);
+  if ((2 * l * pairs + tile - 1) / tile > INT32_MAX) {
+    set_last_error("too many work-groups for one launch");
+    return SPGEMM_EOVERFLOW;
+  }
   if (algorithm == SPGEMM_MERGE_PATH && tile / threads > MERGE_PATH_EMAX) {
     set_last_error("merge path holds at most 32 outputs per thread: use more threads");
     return SPGEMM_EINVAL;
