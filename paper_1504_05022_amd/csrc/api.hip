@@ -589,6 +589,16 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   ea.ct_val = ct_val;
   ea.rownnz = p->rownnz;
 
+  // ---- bin group 4: the four range bins, the largest first: its kernel
+  // runs long enough for the host to queue the short ones behind it
+  stage_begin(p, SPGEMM_T_MEDIUM, s);
+  for (int b = 36; b >= 33; --b) {
+    const int cap = static_cast<int>(next_pow2(p->be.e[b - 32]));
+    const int64_t r0 = S.bin_off[b], r1 = S.bin_off[b + 1];
+    if (launch_esc<T>(ea, p->binlist + r0, r1 - r0, cap, p->n, s))
+      return fail(SPGEMM_EINVAL, "no ESC kernel for this capacity");
+  }
+  stage_end(p, SPGEMM_T_MEDIUM, s);
   // ---- stage 3, bin groups 2-3: one launch per power-of-two capacity
   stage_begin(p, SPGEMM_T_TINY, s);
   if (p->opt.tiny_heap) {
@@ -610,15 +620,6 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     }
   }
   stage_end(p, SPGEMM_T_TINY, s);
-  // ---- bin group 4: the four range bins
-  stage_begin(p, SPGEMM_T_MEDIUM, s);
-  for (int b = 33; b <= 36; ++b) {
-    const int cap = static_cast<int>(next_pow2(p->be.e[b - 32]));
-    const int64_t r0 = S.bin_off[b], r1 = S.bin_off[b + 1];
-    if (launch_esc<T>(ea, p->binlist + r0, r1 - r0, cap, p->n, s))
-      return fail(SPGEMM_EINVAL, "no ESC kernel for this capacity");
-  }
-  stage_end(p, SPGEMM_T_MEDIUM, s);
 
   // ---- bin group 5: long rows (merge method, split over work-groups)
   int64_t pool_entries = 0;
