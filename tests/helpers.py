@@ -54,7 +54,7 @@ def read_golden(path):
             if not line:
                 continue
             parts = line.split()
-            if parts[0].isalpha():
+            if parts[0][0].isalpha():
                 cur = parts[0]
                 mats[cur] = (int(parts[1]), int(parts[2]), [])
             else:

@@ -499,3 +499,127 @@ def test_merge_pairs_worked_example():
     ko, vo = oracle.merge_pairs(k, v, 4)
     assert ko.tolist() == [0, 1, 4, 4, 4, 5, 9, 9]
     assert vo.tolist() == [20, 10, 11, 12, 21, 22, 13, 23]
+
+
+def _golden_rounding():
+    g = read_golden(os.path.join(GOLD, "binary32_rounding.txt"))
+    return g["A"], g["B"], g["C32"], g["C64"]
+
+
+def test_f32_accumulator_sequential_rounding():
+    """Per-step binary32 rounding in ascending j (hand-worked fixture): ties
+    to even at every addition, products rounded before they are added."""
+    A, B, C32, C64 = _golden_rounding()
+    r32 = oracle.spgemm(T(A.astype(np.float32)), T(B.astype(np.float32)), acc32=True)
+    assert r32.val.dtype == np.float32
+    assert csr_equal_structure(r32.row_ptr, r32.col_idx, C32.row_ptr, C32.col_idx)
+    assert np.array_equal(r32.val, C32.val.astype(np.float32))
+    r64 = oracle.spgemm(T(A), T(B))
+    assert np.array_equal(r64.val, C64.val)
+
+
+def _round_f32(x):
+    """Round an exact rational to binary32, nearest, ties to even."""
+    from fractions import Fraction
+    c = np.float32(float(x))
+    best = None
+    for cand in (np.nextafter(c, np.float32(-np.inf)), c, np.nextafter(c, np.float32(np.inf))):
+        d = abs(Fraction(float(cand)) - x)
+        key = (d, int(np.float32(cand).view(np.uint32)) & 1)
+        if best is None or key < best[0]:
+            best = (key, cand)
+    return np.float32(best[1])
+
+
+def test_f32_rounding_fixture_rejects_planted_variants():
+    """Plausible wrong binary32 accumulators fail the fixture: summing in
+    binary64 and rounding once, adding in descending j, or fusing each
+    multiply with its add (one rounding)."""
+    from fractions import Fraction
+    A, B, C32, _ = _golden_rounding()
+    f = np.float32
+    want = list(C32.val.astype(np.float32))
+
+    def row_terms(i):
+        out = []
+        for p in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            j = A.col_idx[p]
+            for q in range(B.row_ptr[j], B.row_ptr[j + 1]):
+                out.append((f(A.val[p]), f(B.val[q])))
+        return out
+
+    def sequential(i):
+        s = f(0.0)
+        for a, b in row_terms(i):
+            s = f(s + f(a * b))
+        return s
+
+    def acc64_round_once(i):
+        s = 0.0
+        for a, b in row_terms(i):
+            s += float(f(a * b))
+        return f(s)
+
+    def descending(i):
+        s = f(0.0)
+        for a, b in reversed(row_terms(i)):
+            s = f(s + f(a * b))
+        return s
+
+    def fused(i):
+        s = f(0.0)
+        for a, b in row_terms(i):
+            s = _round_f32(Fraction(float(s)) + Fraction(float(a)) * Fraction(float(b)))
+        return s
+
+    assert [sequential(i) for i in range(3)] == want
+    for bad, row in ((acc64_round_once, 0), (descending, 1), (fused, 2)):
+        assert bad(row) != want[row], bad.__name__
+
+
+def _fake_ref(val, absval):
+    return oracle.OracleResult(1, len(val), np.array([0, len(val)], np.int64),
+                               np.arange(len(val), dtype=np.int32), np.asarray(val, np.float64),
+                               np.asarray(absval, np.float64), np.array([len(val)], np.int64))
+
+
+def test_value_error_known_answers():
+    """The componentwise metric |c - c*| / (|A||B|)_ik on hand-made cases:
+    a known scaled error, an entry whose exact sum cancels to zero (scaled
+    by its magnitude sum, left out of the plain relative error), and entries
+    whose magnitude sum is zero (must be exactly zero, else infinite)."""
+    # c* = [1, 2, 0 (cancelled: +1 - 1), 0 (all products zero)]
+    ref = _fake_ref([1.0, 2.0, 0.0, 0.0], [2.0, 4.0, 2.0, 0.0])
+    scaled, plain = oracle.value_error([1.0 + 1e-3, 2.0, 0.0, 0.0], ref)
+    assert scaled == pytest.approx(5e-4, rel=1e-12)
+    assert plain == pytest.approx(1e-3, rel=1e-9)
+    # an error on the cancelled entry is scaled by its magnitude sum 2
+    scaled, plain = oracle.value_error([1.0, 2.0, 1e-15, 0.0], ref)
+    assert scaled == pytest.approx(5e-16, rel=1e-12)
+    assert plain == 0.0
+    # a nonzero value where every product is zero
+    scaled, plain = oracle.value_error([1.0, 2.0, 0.0, 1e-300], ref)
+    assert scaled == float("inf") and plain == float("inf")
+    # exact agreement
+    assert oracle.value_error([1.0, 2.0, 0.0, 0.0], ref) == (0.0, 0.0)
+
+
+def test_value_error_rejects_planted_metrics():
+    """Scaling by |c*| instead of the magnitude sum, or dropping the
+    zero-magnitude rule, gives a different answer than the metric on the
+    fixture's cancelled and all-zero entries."""
+    ref = _fake_ref([1.0, 0.0, 0.0], [2.0, 2.0, 0.0])
+    good = [1.0, 1e-15, 0.0]       # error only on the cancelled entry
+    bad = [1.0, 1e-15, 1e-300]     # and a value where every product is zero
+    assert oracle.value_error(good, ref)[0] == pytest.approx(5e-16, rel=1e-12, abs=0)
+    assert oracle.value_error(bad, ref)[0] == float("inf")
+    d_good = np.abs(np.asarray(good) - ref.val)
+    d_bad = np.abs(np.asarray(bad) - ref.val)
+    # planted: scaled by |c*| (the cancelled entry has c* = 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        by_value = float(np.max(d_good / np.abs(ref.val)))
+    assert by_value != pytest.approx(5e-16, rel=1e-6, abs=0)
+    # planted: zero-magnitude entries skipped instead of required to be 0
+    keep = ref.absval > 0
+    no_zero_rule = float(np.max(d_bad[keep] / ref.absval[keep]))
+    assert no_zero_rule != float("inf")
