@@ -41,6 +41,12 @@ def check(A, B, exact=True, **opts):
     assert np.array_equal(ci, ref.col_idx), "col_idx differs"
     assert info.nnz_c == ref.nnz
     assert info.flops == ref.flops
+    assert info.nnz_hat == int(ref.u.sum())
+    if "bin_edges" not in opts and "long_slot" not in opts:
+        # Algorithm 3 with the paper's thresholds: bins and the size of C~
+        b, _, nnz_tilde = oracle.bins(ref.u)
+        assert list(info.bin_count) == np.bincount(b, minlength=38).tolist()
+        assert info.nnz_tilde == nnz_tilde
     err, rel = oracle.value_error(v, ref)
     print("  nnz(C) %d, flops %d, max scaled err %.3g, max rel err %.3g" %
           (ref.nnz, ref.flops, err, rel), flush=True)
@@ -285,18 +291,22 @@ def test_one_call_multiply_matches_plan():
     assert list(i2.bin_count) == list(info.bin_count)
 
 
-def test_options_do_not_change_result():
-    # same product segments throughout (seg fixed), so even split rows are
-    # summed identically
+@pytest.mark.parametrize("seg", [0, 4096])
+def test_options_do_not_change_result(seg):
+    """Bin thresholds, level-1 size and stage timers change neither the
+    structure nor any value: with the default segments (seg = 0, what the
+    benchmark runs) and with 4096-product segments."""
     A, _ = S.config2(n=8000, cap=300)
-    (rp0, ci0, v0), _ = check(A, A, seg=4096)
-    (rp1, ci1, v1), _ = check(A, A, seg=4096, bin_edges=(16, 48, 100, 300, 700))
-    (rp2, ci2, v2), _ = check(A, A, seg=4096, bin_edges=(8, 16, 32, 64, 128), l1_cap=7168)
+    (rp0, ci0, v0), _ = check(A, A, seg=seg)
+    (rp1, ci1, v1), _ = check(A, A, seg=seg, bin_edges=(16, 48, 100, 300, 700))
+    (rp2, ci2, v2), _ = check(A, A, seg=seg, bin_edges=(8, 16, 32, 64, 128), l1_cap=7168)
     # stage timers (all, then two) do not change the result
-    (rp4, ci4, v4), _ = check(A, A, seg=4096, timing=1)
-    (rp5, ci5, v5), _ = check(A, A, seg=4096, timing=1, timing_mask=(1 << 8) | (1 << 10))
+    (rp4, ci4, v4), _ = check(A, A, seg=seg, timing=1)
+    (rp5, ci5, v5), _ = check(A, A, seg=seg, timing=1, timing_mask=(1 << 8) | (1 << 10))
     for ci, v in ((ci1, v1), (ci2, v2), (ci4, v4), (ci5, v5)):
         assert np.array_equal(ci, ci0) and np.array_equal(v, v0)
+    if seg:
+        return
     # a smaller level-1 sequence spills more often: same structure, values
     # within tolerance (checked inside check())
     (rp3, ci3, v3), _ = check(A, A, exact=False, long_slot=8, l1_cap=2048)
