@@ -27,13 +27,26 @@ METRIC = "SpGEMM GFLOP/s and % HBM roofline; batched/backward vs plain on 1 MI35
 WORKLOAD = ("irregular C=A*A, A 200000x200000 CSR, power-law row degrees "
             "(exponent 2.1, mean 16, cap 20000), uniform distinct columns, FP64 U[-1,1]")
 
-# long-row plan of the library's defaults (Algorithm 3 group 5, one-wavefront
-# segments and column ranges)
+# window method for long rows (Algorithm 3 group 5): the library's plan
 LONG_MIN = 512
-WAVE_TILE = 1024
-MAX_SEGS = 512
-RANGE_TARGET = WAVE_TILE // 4
-MIN_SHIFT, MAX_SHIFT = 4, 30
+WIN_STAGE, WIN_SEG, WIN_TARGET, WIN_DIRECT = 2048, 1024, 1536, 2048
+WIN_BITMAP_LOG, WIN_SPLIT, WIN_MAX_PIECES = 18, 65536, 4096
+
+
+def win_plan(u, n, s):
+    """(mode, items, shift, segments) of a long row, as the library plans it:
+    'DS' direct sparse, 'DD' direct dense, 'PT' partitioned, None."""
+    dl = 11 if s == 8 else 12
+    if n <= (1 << dl):
+        return "DD", -(-u // WIN_SPLIT), 0, 0
+    if u <= WIN_DIRECT and n <= (1 << WIN_BITMAP_LOG):
+        return "DS", 1, 0, 0
+    w = -(-(n * WIN_TARGET) // u)
+    sh = min(max(int(math.ceil(math.log2(max(w, 1)))), dl), WIN_BITMAP_LOG)
+    R = -(-n // (1 << sh))
+    if R > WIN_MAX_PIECES:
+        return None, 0, 0, 0
+    return "PT", R, sh, -(-u // WIN_SEG)
 
 
 def parse():
@@ -67,10 +80,9 @@ def copy_probe(mib):
 
 # files the long-row kernels are compiled from: counter figures stay valid
 # only while these are unchanged
-KERNEL_SOURCES = ("paper_1504_05022_amd/csrc/long.hip", "paper_1504_05022_amd/csrc/common.hpp",
-                  "paper_1504_05022_amd/csrc/internal.hpp", "paper_1504_05022_amd/csrc/radix.hpp",
-                  "include/spgemm.h")
-COUNTERS = os.path.join(ROOT, "profiles", "k_combine_w_irregular_AxA_200k_hbm_counters.md")
+KERNEL_SOURCES = ("paper_1504_05022_amd/csrc/window.hip", "paper_1504_05022_amd/csrc/common.hpp",
+                  "paper_1504_05022_amd/csrc/internal.hpp", "include/spgemm.h")
+COUNTERS = os.path.join(ROOT, "profiles", "window_kernels_irregular_AxA_200k_hbm_counters.md")
 
 
 def measured_traffic(kernel):
@@ -109,57 +121,40 @@ def ranges_to_index(starts, lens):
     return off + np.arange(tot, dtype=np.int64)
 
 
-def wave_kernel_bytes(A, B, crp, cci, s):
-    """Algorithmic bytes of the first passes of the two one-wavefront
-    long-row kernels.
+def window_kernel_bytes(A, B, crp, s):
+    """Algorithmic bytes of one launch of each window-method kernel.
 
-    Segment kernel (first pass: the 512-product segments of rows longer
-    than 1024 products), per segment: its A entries (P, column, value, B's
-    row pointer: 16 + s bytes each), the gathered B entries (4 + s each) and
-    the segment's products plus its range starts, which it writes.
-    Range kernel (its first pass, 512-entry wavefront sorts), per column
-    range of a split row: its entries (4 + s each, only if it holds at most
-    512 of them; larger ranges go on to the next pass), its result and piece
-    record; per split row, the range-start table once (4 bytes per range
-    boundary and segment: a range reads the row of its own start and of the
-    next range's start, so each row is counted once)."""
+    Per A entry of a long row read by a kernel: column, value, two entries of
+    the product scan P and two of B's row pointers (16 + s bytes; the
+    symbolic kernel skips the value).  Per product: the B entry it gathers
+    (4 + s; the symbolic kernel reads the column only), or the partial entry
+    (key 4 + s) for partitioned rows.  Partition kernel: reads the row's A
+    entries and B entries, writes the partials (4 + s per product) and the
+    piece-start table (2 bytes per segment and piece boundary).  Symbolic
+    kernel: columns only, plus the table (two entries per segment and piece)
+    and an 8-byte count per item.  Numeric kernel: A and B entries (direct
+    rows) or partials and table (partitioned rows), and the output entries
+    written into C (4 + s each) -- the compulsory output of the long rows."""
     arp = A.row_ptr.astype(np.int64)
     brp = B.row_ptr.astype(np.int64)
     deg = np.diff(arp)
     bdeg = np.diff(brp)
     n = B.cols
     rows_of = np.repeat(np.arange(A.rows), deg)
-    w = bdeg[A.col_idx]
-    u = np.bincount(rows_of, weights=w, minlength=A.rows).astype(np.int64)
+    u = np.bincount(rows_of, weights=bdeg[A.col_idx], minlength=A.rows).astype(np.int64)
     cnnz = np.diff(crp.astype(np.int64))
-    seg_bytes = 0
-    rng_bytes = 0
+    part = sym = num = 0
     for i in np.nonzero(u > LONG_MIN)[0]:
-        ui = int(u[i])
-        e0, e1 = int(arp[i]), int(arp[i + 1])
-        lens = w[e0:e1]
-        starts = np.cumsum(lens) - lens
-        ends = starts + lens
-        if ui <= WAVE_TILE:
-            continue  # one-item row: the second (1024-product) pass
-        segp = max(WAVE_TILE // 2, -(-ui // MAX_SEGS))
-        if segp > WAVE_TILE // 2:
-            continue  # segments too long for the first pass
-        nseg = -(-ui // segp)
-        wdt = -(-(n * RANGE_TARGET) // ui)
-        shift = min(max(int(math.ceil(math.log2(max(wdt, 1)))), MIN_SHIFT), MAX_SHIFT)
-        npiece = -(-n // (1 << shift))
-        p0 = np.arange(nseg, dtype=np.int64) * segp
-        p1 = np.minimum(p0 + segp, ui)
-        d_seg = np.searchsorted(starts, p1, "left") - np.searchsorted(ends, p0, "right")
-        seg_bytes += int(d_seg.sum()) * (16 + s) + 2 * ui * (4 + s) + nseg * ((npiece + 1) * 4 + 128)
-        js = A.col_idx[e0:e1]
-        cols = B.col_idx[ranges_to_index(brp[js], bdeg[js])]
-        E = np.bincount(cols >> shift, minlength=npiece)
-        r = np.bincount(cci[int(crp[i]):int(crp[i + 1])] >> shift, minlength=npiece)
-        small = E <= WAVE_TILE // 2  # the first (512-entry) wavefront pass
-        rng_bytes += (npiece + 1) * nseg * 4 + int((E[small] + r[small]).sum()) * (4 + s) + npiece * 64
-    return seg_bytes, rng_bytes
+        ui, di, ci = int(u[i]), int(deg[i]), int(cnnz[i])
+        mode, R, sh, nseg = win_plan(ui, n, s)
+        if mode == "PT":
+            part += di * (16 + s) + ui * (4 + s) + ui * (4 + s) + 2 * nseg * (R + 1)
+            sym += ui * 4 + 4 * nseg * R + 8 * R
+            num += ui * (4 + s) + 4 * nseg * R + ci * (4 + s)
+        elif mode is not None:
+            sym += di * 16 + ui * 4 + 8 * R
+            num += di * (16 + s) + ui * (4 + s) + ci * (4 + s)
+    return part, sym, num
 
 
 def memory_accounting(A, crp, info, s):
@@ -398,6 +393,54 @@ def galerkin_orders(torch, S, L, reps):
     return res
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_block(args):
+    """One worker of the host-cores baseline: the oracle, as it stands, on a
+    block of rows of the workload (the worker draws the same seeded matrix).
+    Returns (seconds of the oracle call, flops)."""
+    n, r0, r1 = args
+    import oracle
+    import synthetic as S
+    A, _ = S.config2(n=n) if n != 200000 else S.config2()
+    blk = A.row_slice(r0, r1)
+    t = time.perf_counter()
+    ref = oracle.spgemm(blk.as_tuple(), A.as_tuple())
+    return time.perf_counter() - t, ref.flops
+
+
+def parallel_oracle(n):
+    """The oracle on all host cores at once: the rows split into one block of
+    equal flops per worker process, each running the unchanged oracle; the
+    time is the slowest worker's (they run side by side)."""
+    import multiprocessing as mp
+    import synthetic as S
+    workers = min(16, int(os.environ.get("OMP_NUM_THREADS", "16")), os.cpu_count() or 1)
+    A, _ = S.config2(n=n) if n != 200000 else S.config2()
+    deg = np.diff(A.row_ptr.astype(np.int64))
+    u = np.bincount(np.repeat(np.arange(A.rows), deg), weights=deg[A.col_idx],
+                    minlength=A.rows).astype(np.int64)
+    cu = np.cumsum(u)
+    cuts = [0] + [int(np.searchsorted(cu, cu[-1] * k / workers)) for k in range(1, workers)] \
+        + [A.rows]
+    blocks = [(n, cuts[k], cuts[k + 1]) for k in range(workers) if cuts[k + 1] > cuts[k]]
+    with mp.get_context("spawn").Pool(len(blocks)) as pool:
+        res = pool.map(_oracle_block, blocks)
+    t = max(r[0] for r in res)
+    fl = sum(r[1] for r in res)
+    return {"value": round(fl / t / 1e9, 5), "unit": "GFLOP/s", "cores": len(blocks),
+            "kind": "oracle", "sample": "the full workload once, rows split into %d blocks of "
+            "equal flops, one process each (slowest block %.2f s)" % (len(blocks), t)}
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -419,9 +462,11 @@ def main():
     torch.cuda.synchronize()
     s = 8
 
-    # inside the timed steps only the two candidate dominant kernels carry
-    # event timers (each timed stage adds two event records to the stream)
-    wave_mask = (1 << L.STAGES.index("long_wave")) | (1 << L.STAGES.index("combine_wave"))
+    # inside the timed steps only the three window-method kernels (the
+    # candidates for the dominant kernel) carry event timers (each timed
+    # stage adds two event records to the stream)
+    wave_mask = ((1 << L.STAGES.index("long_wave")) | (1 << L.STAGES.index("long_sym"))
+                 | (1 << L.STAGES.index("combine_wave")))
 
     def step(mask=wave_mask):
         return L.spgemm(dA, dA, return_info=True, timing=1, timing_mask=mask)
@@ -445,6 +490,21 @@ def main():
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
     stage_ms /= args.steps
+    # the same steps with the L2 and Infinity Cache flushed before each (a
+    # 512 MB write, outside the measured time): no input is cache-resident
+    # when a step starts
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    flushed = 0.0
+    for _ in range(args.steps):
+        flush.fill_(1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        C, _ = step()
+        torch.cuda.synchronize()
+        flushed += time.perf_counter() - t
+        del C
+    del flush
+    ms_flushed = flushed * 1e3 / args.steps
     # per-stage breakdown from untimed steps with every stage timer on
     full_ms = np.zeros(L.NSTAGES)
     for _ in range(2):
@@ -459,11 +519,12 @@ def main():
     stages = dict(zip(L.STAGES, [round(float(x), 4) for x in stage_ms]))
     breakdown = dict(zip(L.STAGES, [round(float(x), 4) for x in full_ms]))
 
-    # dominant kernel: the longer of the two one-wavefront long-row kernels
-    seg_bytes, rng_bytes = wave_kernel_bytes(A, A, crp, cci, s)
-    cand = [("k_long_w (512-product segments of split rows, one wavefront each)", seg_bytes,
+    # dominant kernel: the longest of the three window-method kernels
+    part_b, sym_b, num_b = window_kernel_bytes(A, A, crp, s)
+    cand = [("k_wpart (partition of long-row segments into column pieces)", part_b,
              stages["long_wave"]),
-            ("k_combine_w (column ranges of split rows, 512-entry wavefront pass)", rng_bytes,
+            ("k_wsym (symbolic pass of the long-row windows)", sym_b, stages["long_sym"]),
+            ("k_wnum (numeric pass of the long-row windows, into C)", num_b,
              stages["combine_wave"])]
     name, kbytes, kms = max(cand, key=lambda c: c[2])
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
@@ -486,7 +547,13 @@ def main():
                    "long_rows": int(info.bin_count[37])},
         "hbm_compulsory": {"bytes": bytes_comp,
                            "achieved_GBps": round(bytes_comp / (ms * 1e-3) / 1e9, 2),
-                           "frac": round(bytes_comp / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)},
+                           "frac": round(bytes_comp / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                           "target_frac": 0.40,
+                           "flushed_ms_per_step": round(ms_flushed, 4),
+                           "flushed_frac": round(bytes_comp / (ms_flushed * 1e-3) / 1e9
+                                                 / HBM_PEAK_GBS, 5)},
+        "window_kernels_ms": {"k_wpart": stages["long_wave"], "k_wsym": stages["long_sym"],
+                              "k_wnum": stages["combine_wave"]},
         "stage_ms": breakdown,
         "roofline": {"kernel": name, "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -508,7 +575,9 @@ def main():
             del ref
         out["cpu_baseline"] = {"value": round(flops / dt / 1e9, 5), "unit": "GFLOP/s",
                                "cores": 1, "kind": "oracle",
-                               "sample": "the full workload, %d runs (%.1f s)" % (runs, dt)}
+                               "sample": "the full workload, %d runs (%.1f s)" % (runs, dt),
+                               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+                               "host_cores": parallel_oracle(args.n)}
     if not args.no_ext:
         tiny = tiny_rows_ablation(torch, L, dA, int(sum(info.bin_count[2:33])))
         del dA

@@ -115,6 +115,14 @@ typedef struct {
                            kernel per exact size) instead of the wavefront
                            ESC; duplicates are then added in heap order, so
                            values may round differently (plain path only)   */
+  int32_t long_path;    /* method for long rows (bin 37):
+                           0 = column windows (default when seg == 0): each
+                             long row is cut into windows of columns, sized
+                             by a symbolic pass and written straight into C;
+                           1 = product segments and column ranges with the
+                             paper's merge method as fallback (the method
+                             that seg != 0 selects)                          */
+  int32_t pad_;
 } spgemm_options;
 
 #define SPGEMM_NBINS 38
@@ -126,14 +134,18 @@ enum {
   SPGEMM_T_BIN = 1,     /* stage 2: binning, C~ offsets                      */
   SPGEMM_T_TINY = 2,    /* stage 3: rows with u <= edge[0]                   */
   SPGEMM_T_MEDIUM = 3,  /* stage 3: rows in the four range bins              */
-  SPGEMM_T_LONG = 4,    /* stage 3: long rows (all relaunch rounds)          */
+  SPGEMM_T_LONG = 4,    /* stage 3: long rows (all relaunch rounds); window
+                           method: planning, partition and symbolic pass  */
   SPGEMM_T_SCAN = 5,    /* stage 4: row pointers of C                        */
   SPGEMM_T_COPY = 6,    /* stage 4: copy C~ into C                           */
   SPGEMM_T_BACKWARD = 7,/* backward kernels (not read back by compute)       */
-  SPGEMM_T_LONG_WAVE = 8,    /* inside LONG: the one-wavefront segment kernel */
-  SPGEMM_T_COMBINE = 9,      /* stage 3: column ranges of split long rows     */
-  SPGEMM_T_COMBINE_WAVE = 10,/* inside COMBINE: the one-wavefront range kernel*/
-  SPGEMM_T_RESERVED = 11
+  SPGEMM_T_LONG_WAVE = 8,    /* inside LONG: the one-wavefront segment kernel;
+                                window method: the partition kernel          */
+  SPGEMM_T_COMBINE = 9,      /* stage 3: column ranges of split long rows;
+                                window method: the numeric pass into C       */
+  SPGEMM_T_COMBINE_WAVE = 10,/* inside COMBINE: the one-wavefront range kernel;
+                                window method: the numeric window kernel     */
+  SPGEMM_T_LONG_SYM = 11     /* window method: the symbolic window kernel     */
 };
 
 typedef struct {

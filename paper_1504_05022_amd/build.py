@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspgemm.so")
-SOURCES = ["api.hip", "analyze.hip", "esc.hip", "heap.hip", "merge.hip", "long.hip", "compact.hip", "backward.hip",
+SOURCES = ["api.hip", "analyze.hip", "esc.hip", "heap.hip", "merge.hip", "long.hip", "window.hip", "compact.hip", "backward.hip",
            "batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -273,6 +273,13 @@ __global__ __launch_bounds__(256) void k_row_stats(RowStatsArgs a) {
     }
     const int64_t segr = segp < a.ncols ? segp : a.ncols;
     if (segr > a.l1cap - kLongTile) v[9] = segr * nseg;
+    const WinPlan wp = win_plan(ui, a.ncols, a.vbytes);
+    v[10] = wp.nitem;
+    v[11] = wp.nseg;
+    v[12] = wp.table;
+    v[13] = wp.partial;
+    v[14] = wp.dslots;
+    v[15] = wp.mode == WIN_NONE ? 1 : 0;
   }
 #pragma unroll
   for (int k = 0; k < kBlockStats; ++k) {
@@ -372,6 +379,12 @@ __global__ __launch_bounds__(256) void k_summary(const int64_t *P, int64_t nnzA,
       case 7: sum->pool_single = x; break;
       case 8: sum->sum_r_multi = x; break;
       case 9: sum->spill_bound = x; break;
+      case 10: sum->w_items = x; break;
+      case 11: sum->w_segs = x; break;
+      case 12: sum->w_table = x; break;
+      case 13: sum->w_partial = x; break;
+      case 14: sum->w_dslots = x; break;
+      case 15: sum->w_none = x; break;
     }
   }
 }

@@ -295,6 +295,7 @@ int check_options(const spgemm_options &o) {
       o.l1_cap != 7168)
     return fail(SPGEMM_EINVAL, "l1_cap must be 0, 2048, 3072, 5120 or 7168");
   if (o.pool_entries < 0) return fail(SPGEMM_EINVAL, "pool_entries must be >= 0");
+  if (o.long_path < 0 || o.long_path > 1) return fail(SPGEMM_EINVAL, "long_path must be 0 or 1");
   if (o.timing_mask < 0 || o.timing_mask >= (1 << SPGEMM_NSTAGES))
     return fail(SPGEMM_EINVAL, "timing_mask has bits beyond the stage count");
   return SPGEMM_OK;
@@ -447,6 +448,7 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
     ra.be = p->be;
     ra.long_slot = o.long_slot;
     ra.l1cap = p->l1cap;
+    ra.vbytes = dtype_bytes(p->dtype);
     ra.lp = p->lp;
     ra.u = p->u;
     ra.h = p->h;
@@ -511,9 +513,17 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   const int64_t nlong = I.bin_count[LONG_BIN];
   release_compute(p, s);
 
+  // long rows: the window method (default), else product segments and
+  // column ranges with the merge method
+  const bool use_win = nlong > 0 && p->opt.seg == 0 && p->opt.long_path == 0 && S.w_none == 0;
+  const bool legacy = nlong > 0 && !use_win;
   // C~ (hybrid sizes) plus the long-row tables in one allocation
-  const int64_t nitems = nlong > 0 ? S.n_items : 0;
-  const int64_t npieces = nlong > 0 ? S.n_pieces : 0;
+  const int64_t nitems = legacy ? S.n_items : 0;
+  const int64_t npieces = legacy ? S.n_pieces : 0;
+  const int64_t w_items = use_win ? S.w_items : 0;
+  const int64_t w_segs = use_win ? S.w_segs : 0;
+  const int64_t w_slots = use_win ? S.w_dslots : 0;
+  const int64_t w_nwords = (p->n + 31) / 32;
   Layout L;
   const size_t octc = L.add<int32_t>(S.sum_h);
   const size_t octv = L.add<T>(S.sum_h);
@@ -530,12 +540,26 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   const size_t opl = L.add<int32_t>(npieces);
   const size_t ops = L.add<int64_t>(npieces + 1);
   const size_t opp = L.add<int64_t>(scan_part_len(std::max<int64_t>(npieces, 1)));
-  const size_t osp = L.add<int32_t>(nlong > 0 ? S.n_split : 0);
-  const size_t opbc = L.add<int32_t>(nlong > 0 ? S.sum_u_multi : 0);
-  const size_t opbv = L.add<T>(nlong > 0 ? S.sum_u_multi : 0);
-  const size_t oobc = L.add<int32_t>(nlong > 0 ? S.sum_u_multi : 0);
-  const size_t oobv = L.add<T>(nlong > 0 ? S.sum_u_multi : 0);
-  const size_t otmp = L.add<int64_t>(long_table_tmp_len(nlong));
+  const size_t osp = L.add<int32_t>(legacy ? S.n_split : 0);
+  const size_t opbc = L.add<int32_t>(legacy ? S.sum_u_multi : 0);
+  const size_t opbv = L.add<T>(legacy ? S.sum_u_multi : 0);
+  const size_t oobc = L.add<int32_t>(legacy ? S.sum_u_multi : 0);
+  const size_t oobv = L.add<T>(legacy ? S.sum_u_multi : 0);
+  const size_t otmp = L.add<int64_t>(legacy ? long_table_tmp_len(nlong) : 0);
+  // window method
+  const size_t owr = L.add<WinRow>(use_win ? nlong : 0);
+  const size_t owi = L.add<WinWork>(w_items);
+  const size_t ows = L.add<WinWork>(w_segs);
+  const size_t owsl = L.add<int32_t>(w_slots);
+  const size_t owb = L.add<int64_t>(use_win ? 5 * ((nlong + 255) / 256) : 0);
+  const size_t owt = L.add<uint16_t>(use_win ? S.w_table : 0);
+  const size_t owpk = L.add<uint32_t>(use_win ? S.w_partial : 0);
+  const size_t owpv = L.add<T>(use_win ? S.w_partial : 0);
+  const size_t owdb = L.add<uint32_t>(w_slots * w_nwords);
+  const size_t owda = L.add<T>(w_slots * p->n);
+  const size_t owc = L.add<int64_t>(w_items);
+  const size_t owis = L.add<int64_t>(use_win ? w_items + 1 : 0);
+  const size_t owpp = L.add<int64_t>(use_win ? scan_part_len(std::max<int64_t>(w_items, 1)) : 0);
   const size_t ocnt = L.add<LongCounters>(1);
   const size_t ogl = L.add<unsigned int>(nitems);
   const size_t ogl2 = L.add<unsigned int>(npieces);
@@ -574,6 +598,19 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   unsigned int *listw = at<unsigned int>(p->cws, olw);
   unsigned int *list2 = at<unsigned int>(p->cws, ol2);
   unsigned int *list3 = at<unsigned int>(p->cws, ol3);
+  WinRow *wrows = at<WinRow>(p->cws, owr);
+  WinWork *witems = at<WinWork>(p->cws, owi);
+  WinWork *wsegs = at<WinWork>(p->cws, ows);
+  int32_t *wslot = at<int32_t>(p->cws, owsl);
+  int64_t *wbsum = at<int64_t>(p->cws, owb);
+  uint16_t *wtable = at<uint16_t>(p->cws, owt);
+  uint32_t *wpkey = at<uint32_t>(p->cws, owpk);
+  T *wpval = at<T>(p->cws, owpv);
+  uint32_t *wdbits = at<uint32_t>(p->cws, owdb);
+  T *wdacc = at<T>(p->cws, owda);
+  int64_t *wcnt = at<int64_t>(p->cws, owc);
+  int64_t *wiscan = at<int64_t>(p->cws, owis);
+  int64_t *wpart = at<int64_t>(p->cws, owpp);
 
   EscArgs<T> ea;
   ea.arp = A->row_ptr;
@@ -675,7 +712,22 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     launch_long_rownnz(lrows, nlong, pscan, p->rownnz, s);
   };
   int rc;
-  if (nlong > 0) {
+  if (use_win) {
+    // window method: plan, partition, symbolic pass, long-row sizes
+    stage_begin(p, SPGEMM_T_LONG, s);
+    win_plan_launch(p->binlist + S.bin_off[LONG_BIN], nlong, p->u, p->n, static_cast<int>(sizeof(T)),
+                    wbsum, wrows, witems, w_items, wsegs, w_segs, wslot, A->row_ptr, p->P, s);
+    stage_begin(p, SPGEMM_T_LONG_WAVE, s);
+    win_partition<T>(ea, wrows, wsegs, w_segs, wtable, wpkey, wpval, s);
+    stage_end(p, SPGEMM_T_LONG_WAVE, s);
+    stage_begin(p, SPGEMM_T_LONG_SYM, s);
+    win_symbolic<T>(ea, p->n, wrows, witems, w_items, wtable, wpkey, wslot, w_slots, wdbits, wcnt,
+                    s);
+    stage_end(p, SPGEMM_T_LONG_SYM, s);
+    scan_i64(wcnt, w_items, wiscan, wpart, s);
+    win_rownnz(wrows, nlong, wiscan, p->rownnz, s);
+    stage_end(p, SPGEMM_T_LONG, s);
+  } else if (nlong > 0) {
     pool_entries = p->opt.pool_entries
                        ? p->opt.pool_entries
                        : S.pool_single + 3 * S.spill_bound + 65536;
@@ -747,8 +799,8 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     unsigned int *fl = fail_a, *fl_other = fail_b;
     for (;;) {
       if ((rc = read_status()) != SPGEMM_OK) return rc;
-      const unsigned int nf1 = nlong > 0 ? p->hstat->fail_count : 0u;
-      const unsigned int nf2 = nlong > 0 ? p->hstat->fail2 : 0u;
+      const unsigned int nf1 = legacy ? p->hstat->fail_count : 0u;
+      const unsigned int nf2 = legacy ? p->hstat->fail2 : 0u;
       if (nf1 == 0 && nf2 == 0) break;
       if (++I.realloc_rounds > 64) return fail(SPGEMM_ENOMEM, "long-row pool keeps overflowing");
       pool_entries *= 2;
@@ -783,11 +835,12 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   }
   const int64_t nnz = p->hstat->nnz_c;
   if (nnz >= (int64_t(1) << 31)) return fail(SPGEMM_EOVERFLOW, "nnz(C) exceeds 2^31 - 1");
-  I.pool_used = nlong > 0 ? static_cast<int64_t>(p->hstat->pool_used) : 0;
+  I.pool_used = legacy ? static_cast<int64_t>(p->hstat->pool_used) : 0;
+  I.long_items = use_win ? S.w_items : (nlong > 0 ? S.n_items : 0);
   I.pool_entries = pool_entries;
   // device scratch held now: analysis, C~ and long-row tables, pool chunks
   I.bytes_scratch = static_cast<int64_t>(p->ws_bytes + p->cws_bytes);
-  for (int64_t e = pool_entries, k = 0; k <= I.realloc_rounds && nlong > 0; ++k, e /= 2)
+  for (int64_t e = pool_entries, k = 0; k <= I.realloc_rounds && legacy; ++k, e /= 2)
     I.bytes_scratch += static_cast<int64_t>(pool_chunk_bytes(e, sizeof(T)));
 
   // ---- stage 4b: allocate C and copy C~ into it
@@ -797,6 +850,16 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   if (!cval) {
     p->al.put(ccol, s);
     return fail(SPGEMM_ENOMEM, "allocation of C failed");
+  }
+  if (use_win) {
+    // numeric pass of the long rows, straight into C
+    stage_begin(p, SPGEMM_T_COMBINE, s);
+    stage_begin(p, SPGEMM_T_COMBINE_WAVE, s);
+    win_numeric<T>(ea, p->n, wrows, witems, w_items, wtable, wpkey, wpval, wslot, w_slots, wdbits,
+                   wdacc, wiscan, p->rowoff, static_cast<int32_t *>(ccol), static_cast<T *>(cval),
+                   s);
+    stage_end(p, SPGEMM_T_COMBINE_WAVE, s);
+    stage_end(p, SPGEMM_T_COMBINE, s);
   }
   stage_begin(p, SPGEMM_T_COPY, s);
   CompactArgs<T> ca;
@@ -862,7 +925,8 @@ extern "C" int spgemm_compute(spgemm_plan plan, const spgemm_csr *A, const spgem
     // waits only for the timed stages (the copy into C may still run)
     static const int kComputeStages[] = {SPGEMM_T_TINY,   SPGEMM_T_MEDIUM,    SPGEMM_T_LONG,
                                          SPGEMM_T_SCAN,   SPGEMM_T_COPY,      SPGEMM_T_LONG_WAVE,
-                                         SPGEMM_T_COMBINE, SPGEMM_T_COMBINE_WAVE};
+                                         SPGEMM_T_COMBINE, SPGEMM_T_COMBINE_WAVE,
+                                         SPGEMM_T_LONG_SYM};
     for (int st : kComputeStages) {
       p->info.stage_ms[st] = 0.f;
       if (p->stage_mask & (1u << st)) {

@@ -48,6 +48,12 @@ struct Summary {
   int64_t pool_single;        // pool entries for final blocks of one-item rows above kOneShot
   int64_t sum_r_multi;        // sum of min(u_i, n) over multi-item rows
   int64_t spill_bound;        // sum of min(segment, n) over items that may spill L1
+  int64_t w_items;            // window path: items
+  int64_t w_segs;             // window path: partition segments
+  int64_t w_table;            // window path: piece-start table entries
+  int64_t w_partial;          // window path: partial entries
+  int64_t w_dslots;           // window path: dense partial rows
+  int64_t w_none;             // long rows without a window plan
   int32_t err;                // nonzero: input validation failed
   int32_t pad;
 };
@@ -103,6 +109,105 @@ __host__ __device__ inline void long_row_plan(int64_t u, int64_t n, const LongPa
   npiece = static_cast<int32_t>((n + (int64_t(1) << shift) - 1) >> shift);
   if (npiece < 1) npiece = 1;
 }
+
+// ------------------------------------------------- window path (long rows)
+// The default method for long rows computes each row of C in windows of
+// columns ("items"), each by one work-group that orders the window's
+// products with a counting sort in LDS and folds every column in
+// Gustavson's order.  A symbolic pass (one bit per column) sizes every item
+// first, so the numeric pass writes straight into C.  Three row plans:
+//  * DIRECT SPARSE: u <= kWinDirect and n <= 2^kWinBitmapLog: one item,
+//    products gathered straight from the B rows;
+//  * DIRECT DENSE: n <= the dense window (2048 binary64 / 4096 binary32
+//    columns): the whole row is one window; rows above kWinSplit products
+//    are cut into product ranges whose dense partial rows are added in
+//    range order afterwards (a fixed order, not Gustavson's);
+//  * PARTITIONED: the row's products are cut into segments of kWinSeg,
+//    each segment scatters its products by column piece (2^shift columns)
+//    into a partial array, and every piece is then one item that gathers
+//    its share of all segments.
+constexpr int kWinStage = 2048;     // products staged in LDS per chunk
+constexpr int kWinSeg = 1024;       // products per partition segment (<= kWinStage / 2)
+constexpr int kWinSegLog = 10;
+constexpr int kWinTarget = 1536;    // expected products per sparse piece
+constexpr int kWinDirect = 2048;    // direct sparse rows: at most this many products
+constexpr int kWinBitmapLog = 18;   // symbolic bitmaps: at most 2^18 columns per item
+constexpr int kWinSplit = 65536;    // direct dense rows: products per item
+constexpr int kWinMaxPieces = 4096; // pieces per partitioned row
+constexpr int kWinBuckets = 2048;   // buckets of the sparse counting sort
+constexpr int kWinBucketLog = 11;
+
+enum { WIN_DS = 0, WIN_DD = 1, WIN_PT = 2, WIN_NONE = 3 };
+
+// log2 of the dense window width: its accumulator (value per column) and
+// counters fill the same LDS budget for both value types
+__host__ __device__ inline int win_dense_log(int vbytes) { return vbytes == 8 ? 11 : 12; }
+
+struct WinPlan {
+  int32_t mode;    // WIN_DS, WIN_DD, WIN_PT, or WIN_NONE (no window plan)
+  int32_t nitem;   // items of the row
+  int32_t shift;   // WIN_PT: log2 of the piece width
+  int32_t nseg;    // WIN_PT: segments
+  int64_t table;   // WIN_PT: entries of the piece-start table, nseg * (nitem + 1)
+  int64_t partial; // WIN_PT: partial entries (u)
+  int64_t dslots;  // WIN_DD with several items: dense partial rows
+};
+
+__host__ __device__ inline WinPlan win_plan(int64_t u, int64_t n, int vbytes) {
+  WinPlan p{};
+  p.mode = WIN_NONE;
+  if (u <= 0) return p;
+  const int dl = win_dense_log(vbytes);
+  if (n <= (int64_t(1) << dl)) {
+    p.mode = WIN_DD;
+    p.nitem = static_cast<int32_t>((u + kWinSplit - 1) / kWinSplit);
+    p.dslots = p.nitem > 1 ? p.nitem : 0;
+    return p;
+  }
+  if (u <= kWinDirect && n <= (int64_t(1) << kWinBitmapLog)) {
+    p.mode = WIN_DS;
+    p.nitem = 1;
+    return p;
+  }
+  const int64_t w = (n * kWinTarget + u - 1) / u;
+  int32_t sh = ceil_log2_i64(w > 1 ? w : 1);
+  if (sh < dl) sh = dl;
+  if (sh > kWinBitmapLog) sh = kWinBitmapLog;
+  const int64_t R = (n + (int64_t(1) << sh) - 1) >> sh;
+  if (R > kWinMaxPieces) return p;  // column space too wide for this plan
+  p.mode = WIN_PT;
+  p.nitem = static_cast<int32_t>(R);
+  p.shift = sh;
+  p.nseg = static_cast<int32_t>((u + kWinSeg - 1) / kWinSeg);
+  p.table = static_cast<int64_t>(p.nseg) * (R + 1);
+  p.partial = u;
+  return p;
+}
+
+struct WinRow {
+  int32_t row;
+  int32_t mode;
+  int32_t nitem;
+  int32_t shift;
+  int32_t nseg;
+  int32_t pad;
+  int64_t u;
+  int64_t item0;   // first item
+  int64_t seg0;    // WIN_PT: first segment
+  int64_t pbase;   // WIN_PT: first partial entry
+  int64_t tbase;   // WIN_PT: first piece-start table entry
+  int64_t dslot0;  // WIN_DD with several items: first dense partial row
+};
+
+// An item (k-th of its row) or a segment (k-th of its row) of the window
+// path; e0 is the entry of A holding the item's / segment's first product
+// (direct dense product ranges and segments).
+struct WinWork {
+  int32_t wrow;
+  int32_t k;
+  int32_t e0;
+  int32_t pad;
+};
 
 struct LongRow {
   int32_t row;
@@ -215,6 +320,7 @@ struct RowStatsArgs {
   BinEdges be;
   int32_t long_slot;
   int32_t l1cap;
+  int32_t vbytes;  // value size (window plan)
   LongParams lp;
   int64_t *u, *h;
   int32_t *hist;
@@ -223,8 +329,10 @@ struct RowStatsArgs {
   int64_t *bpart;  // per-block partial sums, kBlockStats per block
 };
 // per block: max u, sum u (long), sum min(u,n) (long), items, pieces,
-// sum u (multi), split entries, pool (single), sum min(u,n) (multi), spill
-constexpr int kBlockStats = 10;
+// sum u (multi), split entries, pool (single), sum min(u,n) (multi), spill,
+// then the window plan: items, segments, table entries, partial entries,
+// dense partial rows, rows without a window plan
+constexpr int kBlockStats = 16;
 void launch_row_stats(const RowStatsArgs &a, hipStream_t s);
 // Stable scatter of the rows into their bins.
 void launch_bin_scatter(const int64_t *u, int64_t m, BinEdges be, const int64_t *hist_scan,
@@ -327,6 +435,33 @@ void launch_long_rownnz(const LongRow *lrows, int64_t nlong, const int64_t *psca
                         int64_t *rownnz, hipStream_t s);
 void scan_piece_counts(const Piece *pieces, int64_t n, int64_t *out, int64_t *part,
                        hipStream_t s);
+
+// Window path for long rows (window.hip).  Planning: row records, the
+// item and segment lists (bsum: 5 * ceil(nlong / 256) int64).
+void win_plan_launch(const int32_t *lrows, int64_t nlong, const int64_t *u, int64_t n,
+                     int vbytes, int64_t *bsum, WinRow *rows, WinWork *items, int64_t nitems,
+                     WinWork *segs, int64_t nsegs, int32_t *slot_row, const int32_t *arp,
+                     const int64_t *P, hipStream_t s);
+// Partition segments of partitioned rows into piece buckets.
+template <typename T>
+void win_partition(const EscArgs<T> &e, const WinRow *rows, const WinWork *segs, int64_t nsegs,
+                   uint16_t *table, uint32_t *pkey, T *pval, hipStream_t s);
+// Symbolic pass: output count of every item (cnt), dense partial bitmaps.
+template <typename T>
+void win_symbolic(const EscArgs<T> &e, int64_t n, const WinRow *rows, const WinWork *items,
+                  int64_t nitems, const uint16_t *table, const uint32_t *pkey,
+                  const int32_t *slot_row, int64_t nslots, uint32_t *dbits, int64_t *cnt,
+                  hipStream_t s);
+// Long-row sizes from the scanned item counts.
+void win_rownnz(const WinRow *rows, int64_t nlong, const int64_t *iscan, int64_t *rownnz,
+                hipStream_t s);
+// Numeric pass: every item written to its place in C.
+template <typename T>
+void win_numeric(const EscArgs<T> &e, int64_t n, const WinRow *rows, const WinWork *items,
+                 int64_t nitems, const uint16_t *table, const uint32_t *pkey, const T *pval,
+                 const int32_t *slot_row, int64_t nslots, const uint32_t *dbits, T *dacc,
+                 const int64_t *iscan, const int64_t *rowoff, int32_t *c_col, T *c_val,
+                 hipStream_t s);
 
 template <typename T> struct CompactArgs {
   const int64_t *u;

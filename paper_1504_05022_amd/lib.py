@@ -20,7 +20,7 @@ F32, F64 = 0, 1
 NBINS = 38
 NSTAGES = 12
 STAGES = ("upper", "bin", "tiny", "medium", "long", "scan", "copy", "backward", "long_wave",
-          "combine", "combine_wave", "reserved")
+          "combine", "combine_wave", "long_sym")
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EOVERFLOW", -4: "EHIP", -5: "ESTATE"}
 
@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
                 ("l1_cap", ctypes.c_int32), ("seg", ctypes.c_int64),
                 ("pool_entries", ctypes.c_int64), ("validate", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("timing_mask", ctypes.c_int32),
-                ("tiny_heap", ctypes.c_int32)]
+                ("tiny_heap", ctypes.c_int32), ("long_path", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

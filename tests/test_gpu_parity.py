@@ -52,13 +52,20 @@ def check(A, B, exact=True, **opts):
           (ref.nnz, ref.flops, err, rel), flush=True)
     assert err <= TOL[np.dtype(A.val.dtype)]
     if exact:
-        # rows summed in the oracle's order: not split into segments and not
-        # spilling out of the level-1 sequence
-        l1cap = opts.get("l1_cap") or (5120 if A.val.dtype == np.float64 else 7168)
-        seg = opts.get("seg", 0)
-        segp = np.inf if seg is not None and seg < 0 else (seg or 1024)
         u = ref.u
-        ok_rows = (u <= segp) & (np.minimum(u, B.cols) <= l1cap - 1024)
+        seg = opts.get("seg", 0)
+        if not seg and not opts.get("long_path", 0):
+            # column windows: every row in Gustavson's order, except rows
+            # of more than 65536 products into at most one dense window of
+            # columns (product ranges added in range order)
+            dense_w = 2048 if A.val.dtype == np.float64 else 4096
+            ok_rows = ~((B.cols <= dense_w) & (u > 65536))
+        else:
+            # rows summed in the oracle's order: not split into segments and
+            # not spilling out of the level-1 sequence
+            l1cap = opts.get("l1_cap") or (5120 if A.val.dtype == np.float64 else 7168)
+            segp = np.inf if seg is not None and seg < 0 else (seg or 1024)
+            ok_rows = (u <= segp) & (np.minimum(u, B.cols) <= l1cap - 1024)
         mask = np.repeat(ok_rows, np.diff(ref.row_ptr))
         if A.val.dtype == np.float64:
             assert np.array_equal(v[mask], ref.val[mask]), "binary64 values differ from sequential sums"
@@ -397,3 +404,51 @@ def test_backward_matches_oracle(dtype, ncols):
     assert np.all(np.abs(gA.cpu().numpy().astype(np.float64) - ra) <= tol * sa + 0.0)
     assert np.all(np.abs(gB.cpu().numpy().astype(np.float64) - rb) <= tol * sb + 0.0)
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_window_method_row_plans(dtype):
+    """The default method for long rows (column windows), one case per row
+    plan, every value Gustavson's sequential sum: rows of up to 2048
+    products as one sparse window; longer rows partitioned into pieces of
+    2^shift columns -- dense pieces (one accumulator window), sparse pieces
+    in one chunk, and sparse pieces whose products crowd into few columns
+    and overflow one chunk (then swept in dense sub-windows)."""
+    targets = [513, 700, 1500, 2048, 2049, 3000, 5000, 20000, 60000]
+    A, B = S.crafted_rows(targets * 2, n=60000, dtype=dtype)
+    check(A, B)
+    # products crowded into columns [0, 3000) of 60000: overflowing pieces
+    A, B = S.crafted_rows([2500, 5000, 9000, 30000], n=60000, col_range=3000, dtype=dtype)
+    check(A, B)
+    # many duplicates in few columns (heapsort path of large buckets)
+    A, B = S.crafted_rows([3000, 5000, 1200], n=60000, col_range=40, dtype=dtype)
+    check(A, B)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_window_method_dense_rows(dtype):
+    """C with at most 2048 (binary64) / 4096 (binary32) columns: every long
+    row is one dense window; rows above 65536 products are cut into product
+    ranges whose dense partial rows are added in range order (values within
+    tolerance), the others are exact."""
+    n, big = (1500, 80000) if dtype == np.float64 else (3500, 120000)
+    A, B = S.crafted_rows([600, 3000, 40000, 70000, big, 513], n=n, dtype=dtype)
+    (rp, ci, v), info = check(A, B, exact=False)
+    ref = oracle.spgemm(A.astype(np.float64).as_tuple(), B.astype(np.float64).as_tuple())
+    exact_rows = ref.u <= 65536
+    mask = np.repeat(exact_rows, np.diff(ref.row_ptr))
+    if dtype == np.float64:
+        assert np.array_equal(v[mask], ref.val[mask])
+    else:
+        r32 = oracle.spgemm(A.as_tuple(), B.as_tuple(), acc32=True)
+        assert np.array_equal(v[mask], r32.val[mask])
+
+
+def test_window_method_matches_segment_method():
+    """The two long-row methods give the same structure, and the same values
+    wherever both sum in Gustavson's order (workload-2 structure)."""
+    A, _ = S.config2(n=30000, cap=5000)
+    (rp0, ci0, v0), i0 = check(A, A)
+    (rp1, ci1, v1), i1 = check(A, A, long_path=1)
+    assert np.array_equal(rp0, rp1) and np.array_equal(ci0, ci1)
+    assert np.array_equal(v0, v1)
