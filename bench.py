@@ -27,10 +27,22 @@ METRIC = "SpGEMM GFLOP/s and % HBM roofline; batched/backward vs plain on 1 MI35
 WORKLOAD = ("irregular C=A*A, A 200000x200000 CSR, power-law row degrees "
             "(exponent 2.1, mean 16, cap 20000), uniform distinct columns, FP64 U[-1,1]")
 
-# window method for long rows (Algorithm 3 group 5): the library's plan
+# long rows (Algorithm 3 group 5): the library's plans.  Merge method
+# (default when B has more columns than a dense window): one-wavefront
+# segments and column ranges; column windows: pieces of 2^shift columns.
 LONG_MIN = 512
-WIN_STAGE, WIN_SEG, WIN_TARGET, WIN_DIRECT = 2048, 1024, 1536, 2048
-WIN_BITMAP_LOG, WIN_SPLIT, WIN_MAX_PIECES = 18, 65536, 4096
+WAVE_TILE = 1024
+MAX_SEGS = 512
+RANGE_TARGET = WAVE_TILE // 4
+MIN_SHIFT, MAX_SHIFT = 4, 30
+WIN_SEG, WIN_TARGET, WIN_DIRECT = 512, 512, 1024
+WIN_BITMAP_LOG, WIN_SPLIT, WIN_MAX_PIECES = 18, 16384, 1024
+
+
+def dense_cols(s):
+    """Columns of the dense window: with at most this many columns in B the
+    library takes column windows for long rows by default."""
+    return 2048 if s == 8 else 4096
 
 
 def win_plan(u, n, s):
@@ -39,11 +51,14 @@ def win_plan(u, n, s):
     dl = 11 if s == 8 else 12
     if n <= (1 << dl):
         return "DD", -(-u // WIN_SPLIT), 0, 0
-    if u <= WIN_DIRECT and n <= (1 << WIN_BITMAP_LOG):
+    if u <= WIN_DIRECT:
         return "DS", 1, 0, 0
-    w = -(-(n * WIN_TARGET) // u)
-    sh = min(max(int(math.ceil(math.log2(max(w, 1)))), dl), WIN_BITMAP_LOG)
+    w = n * WIN_TARGET // u
+    sh = min(int(math.floor(math.log2(w))) if w >= 1 else 0, WIN_BITMAP_LOG)
     R = -(-n // (1 << sh))
+    while R > WIN_MAX_PIECES and sh < WIN_BITMAP_LOG:
+        sh += 1
+        R = -(-n // (1 << sh))
     if R > WIN_MAX_PIECES:
         return None, 0, 0, 0
     return "PT", R, sh, -(-u // WIN_SEG)
@@ -80,9 +95,14 @@ def copy_probe(mib):
 
 # files the long-row kernels are compiled from: counter figures stay valid
 # only while these are unchanged
-KERNEL_SOURCES = ("paper_1504_05022_amd/csrc/window.hip", "paper_1504_05022_amd/csrc/common.hpp",
-                  "paper_1504_05022_amd/csrc/internal.hpp", "include/spgemm.h")
-COUNTERS = os.path.join(ROOT, "profiles", "window_kernels_irregular_AxA_200k_hbm_counters.md")
+KERNEL_SOURCES = ("paper_1504_05022_amd/csrc/long.hip", "paper_1504_05022_amd/csrc/window.hip",
+                  "paper_1504_05022_amd/csrc/common.hpp", "paper_1504_05022_amd/csrc/internal.hpp",
+                  "include/spgemm.h")
+
+
+def counters_file(kernel):
+    """Committed HBM counter summary of a kernel on this workload."""
+    return os.path.join(ROOT, "profiles", "%s_irregular_AxA_200k_hbm_counters.md" % kernel.split()[0])
 
 
 def measured_traffic(kernel):
@@ -92,7 +112,7 @@ def measured_traffic(kernel):
     import hashlib
     try:
         kv = {}
-        for line in open(COUNTERS):
+        for line in open(counters_file(kernel)):
             if ":" in line and not line.startswith(("#", "|", " ")):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
@@ -119,6 +139,58 @@ def ranges_to_index(starts, lens):
         return np.zeros(0, np.int64)
     off = np.repeat(np.asarray(starts, np.int64) - (np.cumsum(lens) - lens), lens)
     return off + np.arange(tot, dtype=np.int64)
+
+
+def merge_kernel_bytes(A, B, crp, cci, s):
+    """Algorithmic bytes of the first passes of the two one-wavefront
+    long-row kernels of the merge method.
+
+    Segment kernel (first pass: the 512-product segments of rows longer
+    than 1024 products), per segment: its A entries (P, column, value, B's
+    row pointer: 16 + s bytes each), the gathered B entries (4 + s each) and
+    the segment's products plus its range starts, which it writes.
+    Range kernel (its first pass, 512-entry wavefront sorts), per column
+    range of a split row: its entries (4 + s each, only if it holds at most
+    512 of them; larger ranges go on to the next pass), its result and piece
+    record; per split row, the range-start table once (4 bytes per range
+    boundary and segment: a range reads the row of its own start and of the
+    next range's start, so each row is counted once)."""
+    arp = A.row_ptr.astype(np.int64)
+    brp = B.row_ptr.astype(np.int64)
+    deg = np.diff(arp)
+    bdeg = np.diff(brp)
+    n = B.cols
+    rows_of = np.repeat(np.arange(A.rows), deg)
+    w = bdeg[A.col_idx]
+    u = np.bincount(rows_of, weights=w, minlength=A.rows).astype(np.int64)
+    seg_bytes = 0
+    rng_bytes = 0
+    for i in np.nonzero(u > LONG_MIN)[0]:
+        ui = int(u[i])
+        e0, e1 = int(arp[i]), int(arp[i + 1])
+        lens = w[e0:e1]
+        starts = np.cumsum(lens) - lens
+        ends = starts + lens
+        if ui <= WAVE_TILE:
+            continue  # one-item row: the second (1024-product) pass
+        segp = max(WAVE_TILE // 2, -(-ui // MAX_SEGS))
+        if segp > WAVE_TILE // 2:
+            continue  # segments too long for the first pass
+        nseg = -(-ui // segp)
+        wdt = -(-(n * RANGE_TARGET) // ui)
+        shift = min(max(int(math.ceil(math.log2(max(wdt, 1)))), MIN_SHIFT), MAX_SHIFT)
+        npiece = -(-n // (1 << shift))
+        p0 = np.arange(nseg, dtype=np.int64) * segp
+        p1 = np.minimum(p0 + segp, ui)
+        d_seg = np.searchsorted(starts, p1, "left") - np.searchsorted(ends, p0, "right")
+        seg_bytes += int(d_seg.sum()) * (16 + s) + 2 * ui * (4 + s) + nseg * ((npiece + 1) * 4 + 128)
+        js = A.col_idx[e0:e1]
+        cols = B.col_idx[ranges_to_index(brp[js], bdeg[js])]
+        E = np.bincount(cols >> shift, minlength=npiece)
+        r = np.bincount(cci[int(crp[i]):int(crp[i + 1])] >> shift, minlength=npiece)
+        small = E <= WAVE_TILE // 2  # the first (512-entry) wavefront pass
+        rng_bytes += (npiece + 1) * nseg * 4 + int((E[small] + r[small]).sum()) * (4 + s) + npiece * 64
+    return seg_bytes, rng_bytes
 
 
 def window_kernel_bytes(A, B, crp, s):
@@ -462,9 +534,9 @@ def main():
     torch.cuda.synchronize()
     s = 8
 
-    # inside the timed steps only the three window-method kernels (the
-    # candidates for the dominant kernel) carry event timers (each timed
-    # stage adds two event records to the stream)
+    # inside the timed steps only the long-row kernels (the candidates for
+    # the dominant kernel) carry event timers (each timed stage adds two
+    # event records to the stream)
     wave_mask = ((1 << L.STAGES.index("long_wave")) | (1 << L.STAGES.index("long_sym"))
                  | (1 << L.STAGES.index("combine_wave")))
 
@@ -519,13 +591,21 @@ def main():
     stages = dict(zip(L.STAGES, [round(float(x), 4) for x in stage_ms]))
     breakdown = dict(zip(L.STAGES, [round(float(x), 4) for x in full_ms]))
 
-    # dominant kernel: the longest of the three window-method kernels
-    part_b, sym_b, num_b = window_kernel_bytes(A, A, crp, s)
-    cand = [("k_wpart (partition of long-row segments into column pieces)", part_b,
-             stages["long_wave"]),
-            ("k_wsym (symbolic pass of the long-row windows)", sym_b, stages["long_sym"]),
-            ("k_wnum (numeric pass of the long-row windows, into C)", num_b,
-             stages["combine_wave"])]
+    # dominant kernel: the longest of the long-row kernels of the method the
+    # library takes for this product
+    if A.cols <= dense_cols(s):
+        part_b, sym_b, num_b = window_kernel_bytes(A, A, crp, s)
+        cand = [("k_wpart (partition of long-row segments into column pieces)", part_b,
+                 stages["long_wave"]),
+                ("k_wsym (symbolic pass of the long-row windows)", sym_b, stages["long_sym"]),
+                ("k_wnum (numeric pass of the long-row windows, into C)", num_b,
+                 stages["combine_wave"])]
+    else:
+        seg_b, rng_b = merge_kernel_bytes(A, A, crp, cci, s)
+        cand = [("k_long_w (512-product segments of split rows, one wavefront each)", seg_b,
+                 stages["long_wave"]),
+                ("k_combine_w (column ranges of split rows, 512-entry wavefront pass)", rng_b,
+                 stages["combine_wave"])]
     name, kbytes, kms = max(cand, key=lambda c: c[2])
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
 
@@ -552,8 +632,7 @@ def main():
                            "flushed_ms_per_step": round(ms_flushed, 4),
                            "flushed_frac": round(bytes_comp / (ms_flushed * 1e-3) / 1e9
                                                  / HBM_PEAK_GBS, 5)},
-        "window_kernels_ms": {"k_wpart": stages["long_wave"], "k_wsym": stages["long_sym"],
-                              "k_wnum": stages["combine_wave"]},
+        "long_row_kernels_ms": {c[0].split()[0]: c[2] for c in cand},
         "stage_ms": breakdown,
         "roofline": {"kernel": name, "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -85,10 +85,12 @@ typedef void (*spgemm_free_fn)(void *ptr, void *ctx, void *stream);
 /* Tuning knobs.  spgemm_default_options() gives the paper's settings
  * (Algorithm 3 thresholds, 256-entry long-row slot, 2x growth).  None of
  * them changes the structure of C.  Every column is summed in the order of
- * Gustavson's algorithm (ascending j) except for long-row work that goes
+ * Gustavson's algorithm (ascending j) except (a) long-row work that goes
  * through the level-1 merge method (work items or output column ranges of
- * more than 4096 entries, or seg < 0): there partial sums are added in a
- * fixed order that may round differently. */
+ * more than 4096 entries, or seg < 0) and (b) with column windows, long
+ * rows of more than 16384 products when B has at most 2048 (binary64) /
+ * 4096 (binary32) columns, which are cut into product ranges: there
+ * partial sums are added in a fixed order that may round differently. */
 typedef struct {
   /* upper row sizes of: the single-size bins (group 3, default 32), then the
    * four range bins of group 4 (defaults 64, 128, 256, 512).  Rows above the
@@ -116,12 +118,16 @@ typedef struct {
                            ESC; duplicates are then added in heap order, so
                            values may round differently (plain path only)   */
   int32_t long_path;    /* method for long rows (bin 37):
-                           0 = column windows (default when seg == 0): each
-                             long row is cut into windows of columns, sized
-                             by a symbolic pass and written straight into C;
-                           1 = product segments and column ranges with the
-                             paper's merge method as fallback (the method
-                             that seg != 0 selects)                          */
+                           0 = automatic (default): column windows when B
+                             has at most 2048 (binary64) / 4096 (binary32)
+                             columns -- every long row then sums into one
+                             dense window of LDS -- else method 1;
+                           1 = product segments and column ranges, with the
+                             paper's merge method as fallback (also what
+                             seg != 0 selects);
+                           2 = column windows: each long row is cut into
+                             windows of columns, sized by a symbolic pass
+                             and written straight into C                     */
   int32_t pad_;
 } spgemm_options;
 

@@ -295,7 +295,7 @@ int check_options(const spgemm_options &o) {
       o.l1_cap != 7168)
     return fail(SPGEMM_EINVAL, "l1_cap must be 0, 2048, 3072, 5120 or 7168");
   if (o.pool_entries < 0) return fail(SPGEMM_EINVAL, "pool_entries must be >= 0");
-  if (o.long_path < 0 || o.long_path > 1) return fail(SPGEMM_EINVAL, "long_path must be 0 or 1");
+  if (o.long_path < 0 || o.long_path > 2) return fail(SPGEMM_EINVAL, "long_path must be 0, 1 or 2");
   if (o.timing_mask < 0 || o.timing_mask >= (1 << SPGEMM_NSTAGES))
     return fail(SPGEMM_EINVAL, "timing_mask has bits beyond the stage count");
   return SPGEMM_OK;
@@ -513,9 +513,12 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   const int64_t nlong = I.bin_count[LONG_BIN];
   release_compute(p, s);
 
-  // long rows: the window method (default), else product segments and
-  // column ranges with the merge method
-  const bool use_win = nlong > 0 && p->opt.seg == 0 && p->opt.long_path == 0 && S.w_none == 0;
+  // long rows: column windows (by default when every long row is a direct
+  // dense row, i.e. B has at most kDenseCols columns), else product
+  // segments and column ranges with the merge method
+  const int64_t kDenseCols = int64_t(1) << win_dense_log(static_cast<int>(sizeof(T)));
+  const bool want_win = p->opt.long_path == 2 || (p->opt.long_path == 0 && p->n <= kDenseCols);
+  const bool use_win = nlong > 0 && p->opt.seg == 0 && want_win && S.w_none == 0;
   const bool legacy = nlong > 0 && !use_win;
   // C~ (hybrid sizes) plus the long-row tables in one allocation
   const int64_t nitems = legacy ? S.n_items : 0;
@@ -560,6 +563,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   const size_t owc = L.add<int64_t>(w_items);
   const size_t owis = L.add<int64_t>(use_win ? w_items + 1 : 0);
   const size_t owpp = L.add<int64_t>(use_win ? scan_part_len(std::max<int64_t>(w_items, 1)) : 0);
+  const size_t owl = L.add<uint32_t>(use_win ? w_items + 1 : 0);
   const size_t ocnt = L.add<LongCounters>(1);
   const size_t ogl = L.add<unsigned int>(nitems);
   const size_t ogl2 = L.add<unsigned int>(npieces);
@@ -611,6 +615,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   int64_t *wcnt = at<int64_t>(p->cws, owc);
   int64_t *wiscan = at<int64_t>(p->cws, owis);
   int64_t *wpart = at<int64_t>(p->cws, owpp);
+  uint32_t *wlist = at<uint32_t>(p->cws, owl);  // [0]: count, then item ids
 
   EscArgs<T> ea;
   ea.arp = A->row_ptr;
@@ -716,13 +721,14 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     // window method: plan, partition, symbolic pass, long-row sizes
     stage_begin(p, SPGEMM_T_LONG, s);
     win_plan_launch(p->binlist + S.bin_off[LONG_BIN], nlong, p->u, p->n, static_cast<int>(sizeof(T)),
-                    wbsum, wrows, witems, w_items, wsegs, w_segs, wslot, A->row_ptr, p->P, s);
+                    wbsum, wrows, witems, w_items, wsegs, w_segs, wslot, w_slots, A->row_ptr, p->P,
+                    s);
     stage_begin(p, SPGEMM_T_LONG_WAVE, s);
     win_partition<T>(ea, wrows, wsegs, w_segs, wtable, wpkey, wpval, s);
     stage_end(p, SPGEMM_T_LONG_WAVE, s);
     stage_begin(p, SPGEMM_T_LONG_SYM, s);
-    win_symbolic<T>(ea, p->n, wrows, witems, w_items, wtable, wpkey, wslot, w_slots, wdbits, wcnt,
-                    s);
+    win_symbolic<T>(ea, p->n, wrows, witems, w_items, wtable, wpkey, wslot, w_slots, wlist + 1,
+                    wlist, wdbits, wcnt, s);
     stage_end(p, SPGEMM_T_LONG_SYM, s);
     scan_i64(wcnt, w_items, wiscan, wpart, s);
     win_rownnz(wrows, nlong, wiscan, p->rownnz, s);
@@ -855,9 +861,9 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     // numeric pass of the long rows, straight into C
     stage_begin(p, SPGEMM_T_COMBINE, s);
     stage_begin(p, SPGEMM_T_COMBINE_WAVE, s);
-    win_numeric<T>(ea, p->n, wrows, witems, w_items, wtable, wpkey, wpval, wslot, w_slots, wdbits,
-                   wdacc, wiscan, p->rowoff, static_cast<int32_t *>(ccol), static_cast<T *>(cval),
-                   s);
+    win_numeric<T>(ea, p->n, wrows, witems, w_items, wtable, wpkey, wpval, wslot, w_slots,
+                   wlist + 1, wlist, wdbits, wdacc, wiscan, p->rowoff,
+                   static_cast<int32_t *>(ccol), static_cast<T *>(cval), s);
     stage_end(p, SPGEMM_T_COMBINE_WAVE, s);
     stage_end(p, SPGEMM_T_COMBINE, s);
   }

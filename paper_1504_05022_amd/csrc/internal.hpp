@@ -111,31 +111,35 @@ __host__ __device__ inline void long_row_plan(int64_t u, int64_t n, const LongPa
 }
 
 // ------------------------------------------------- window path (long rows)
-// The default method for long rows computes each row of C in windows of
-// columns ("items"), each by one work-group that orders the window's
-// products with a counting sort in LDS and folds every column in
-// Gustavson's order.  A symbolic pass (one bit per column) sizes every item
-// first, so the numeric pass writes straight into C.  Three row plans:
-//  * DIRECT SPARSE: u <= kWinDirect and n <= 2^kWinBitmapLog: one item,
-//    products gathered straight from the B rows;
+// Column windows (long_path 2, and the default when B has at most a dense
+// window of columns) compute each long row of C in windows of columns
+// ("items").  A symbolic pass sizes every item first, so the numeric pass
+// writes straight into C.  Three row plans:
 //  * DIRECT DENSE: n <= the dense window (2048 binary64 / 4096 binary32
-//    columns): the whole row is one window; rows above kWinSplit products
-//    are cut into product ranges whose dense partial rows are added in
-//    range order afterwards (a fixed order, not Gustavson's);
+//    columns): the whole row is one window, a dense accumulator in LDS that
+//    one wavefront updates in expansion order; rows above kWinSplit
+//    products are cut into product ranges whose dense partial rows are
+//    added in range order afterwards (a fixed order, not Gustavson's);
+//  * DIRECT SPARSE: u <= kWinDirect: one item, products gathered straight
+//    from the B rows, ordered by a counting sort in LDS and folded in
+//    Gustavson's order by one wavefront;
 //  * PARTITIONED: the row's products are cut into segments of kWinSeg,
-//    each segment scatters its products by column piece (2^shift columns)
-//    into a partial array, and every piece is then one item that gathers
-//    its share of all segments.
-constexpr int kWinStage = 2048;     // products staged in LDS per chunk
-constexpr int kWinSeg = 1024;       // products per partition segment (<= kWinStage / 2)
-constexpr int kWinSegLog = 10;
-constexpr int kWinTarget = 1536;    // expected products per sparse piece
-constexpr int kWinDirect = 2048;    // direct sparse rows: at most this many products
-constexpr int kWinBitmapLog = 18;   // symbolic bitmaps: at most 2^18 columns per item
-constexpr int kWinSplit = 65536;    // direct dense rows: products per item
-constexpr int kWinMaxPieces = 4096; // pieces per partitioned row
-constexpr int kWinBuckets = 2048;   // buckets of the sparse counting sort
-constexpr int kWinBucketLog = 11;
+//    each segment scatters its products stably (expansion order kept inside
+//    every bucket) by column piece (2^shift columns) into a partial array
+//    and records where every piece starts (a piece-start table); a piece
+//    then gathers its share of every segment, in segment order, and is one
+//    item, finished like a direct sparse row.  A piece with more products
+//    than a wavefront stages goes to a work-group kernel, which sweeps it in
+//    dense sub-windows.
+constexpr int kWinStage = 1024;     // products staged in LDS per wavefront item
+constexpr int kWinSeg = 512;        // products per partition segment
+constexpr int kWinTarget = 512;     // expected products per piece
+constexpr int kWinDirect = 1024;    // direct sparse rows: at most this many products
+constexpr int kWinBitmapLog = 18;   // pieces are at most 2^18 columns wide
+constexpr int kWinSplit = 16384;    // direct dense rows: products per item
+constexpr int kWinMaxPieces = 1024; // pieces per partitioned row
+constexpr int kWinBuckets = 512;    // buckets of the wavefront counting sort
+constexpr int kWinBucketLog = 9;
 
 enum { WIN_DS = 0, WIN_DD = 1, WIN_PT = 2, WIN_NONE = 3 };
 
@@ -148,7 +152,7 @@ struct WinPlan {
   int32_t nitem;   // items of the row
   int32_t shift;   // WIN_PT: log2 of the piece width
   int32_t nseg;    // WIN_PT: segments
-  int64_t table;   // WIN_PT: entries of the piece-start table, nseg * (nitem + 1)
+  int64_t table;   // WIN_PT: entries of the piece-start table, (nitem + 1) * nseg
   int64_t partial; // WIN_PT: partial entries (u)
   int64_t dslots;  // WIN_DD with several items: dense partial rows
 };
@@ -164,16 +168,21 @@ __host__ __device__ inline WinPlan win_plan(int64_t u, int64_t n, int vbytes) {
     p.dslots = p.nitem > 1 ? p.nitem : 0;
     return p;
   }
-  if (u <= kWinDirect && n <= (int64_t(1) << kWinBitmapLog)) {
+  if (u <= kWinDirect) {
     p.mode = WIN_DS;
     p.nitem = 1;
     return p;
   }
-  const int64_t w = (n * kWinTarget + u - 1) / u;
-  int32_t sh = ceil_log2_i64(w > 1 ? w : 1);
-  if (sh < dl) sh = dl;
+  // widest power of two that holds at most kWinTarget products on average
+  const int64_t w = n * kWinTarget / u;
+  int32_t sh = 0;
+  while ((int64_t(2) << sh) <= w) ++sh;
   if (sh > kWinBitmapLog) sh = kWinBitmapLog;
-  const int64_t R = (n + (int64_t(1) << sh) - 1) >> sh;
+  int64_t R = (n + (int64_t(1) << sh) - 1) >> sh;
+  while (R > kWinMaxPieces && sh < kWinBitmapLog) {  // wider pieces, fewer of them
+    ++sh;
+    R = (n + (int64_t(1) << sh) - 1) >> sh;
+  }
   if (R > kWinMaxPieces) return p;  // column space too wide for this plan
   p.mode = WIN_PT;
   p.nitem = static_cast<int32_t>(R);
@@ -440,18 +449,20 @@ void scan_piece_counts(const Piece *pieces, int64_t n, int64_t *out, int64_t *pa
 // item and segment lists (bsum: 5 * ceil(nlong / 256) int64).
 void win_plan_launch(const int32_t *lrows, int64_t nlong, const int64_t *u, int64_t n,
                      int vbytes, int64_t *bsum, WinRow *rows, WinWork *items, int64_t nitems,
-                     WinWork *segs, int64_t nsegs, int32_t *slot_row, const int32_t *arp,
-                     const int64_t *P, hipStream_t s);
+                     WinWork *segs, int64_t nsegs, int32_t *slot_row, int64_t nslots,
+                     const int32_t *arp, const int64_t *P, hipStream_t s);
 // Partition segments of partitioned rows into piece buckets.
 template <typename T>
 void win_partition(const EscArgs<T> &e, const WinRow *rows, const WinWork *segs, int64_t nsegs,
                    uint16_t *table, uint32_t *pkey, T *pval, hipStream_t s);
-// Symbolic pass: output count of every item (cnt), dense partial bitmaps.
+// Symbolic pass: output count of every item (cnt), dense partial bitmaps;
+// lists (list_ids, list_count: nitems + 1 entries) the items that the
+// work-group kernels finish.
 template <typename T>
 void win_symbolic(const EscArgs<T> &e, int64_t n, const WinRow *rows, const WinWork *items,
                   int64_t nitems, const uint16_t *table, const uint32_t *pkey,
-                  const int32_t *slot_row, int64_t nslots, uint32_t *dbits, int64_t *cnt,
-                  hipStream_t s);
+                  const int32_t *slot_row, int64_t nslots, uint32_t *list_ids,
+                  uint32_t *list_count, uint32_t *dbits, int64_t *cnt, hipStream_t s);
 // Long-row sizes from the scanned item counts.
 void win_rownnz(const WinRow *rows, int64_t nlong, const int64_t *iscan, int64_t *rownnz,
                 hipStream_t s);
@@ -459,9 +470,9 @@ void win_rownnz(const WinRow *rows, int64_t nlong, const int64_t *iscan, int64_t
 template <typename T>
 void win_numeric(const EscArgs<T> &e, int64_t n, const WinRow *rows, const WinWork *items,
                  int64_t nitems, const uint16_t *table, const uint32_t *pkey, const T *pval,
-                 const int32_t *slot_row, int64_t nslots, const uint32_t *dbits, T *dacc,
-                 const int64_t *iscan, const int64_t *rowoff, int32_t *c_col, T *c_val,
-                 hipStream_t s);
+                 const int32_t *slot_row, int64_t nslots, uint32_t *list_ids,
+                 uint32_t *list_count, const uint32_t *dbits, T *dacc, const int64_t *iscan,
+                 const int64_t *rowoff, int32_t *c_col, T *c_val, hipStream_t s);
 
 template <typename T> struct CompactArgs {
   const int64_t *u;

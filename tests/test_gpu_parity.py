@@ -54,12 +54,14 @@ def check(A, B, exact=True, **opts):
     if exact:
         u = ref.u
         seg = opts.get("seg", 0)
-        if not seg and not opts.get("long_path", 0):
-            # column windows: every row in Gustavson's order, except rows
-            # of more than 65536 products into at most one dense window of
-            # columns (product ranges added in range order)
-            dense_w = 2048 if A.val.dtype == np.float64 else 4096
-            ok_rows = ~((B.cols <= dense_w) & (u > 65536))
+        lp = opts.get("long_path", 0)
+        dense_w = 2048 if A.val.dtype == np.float64 else 4096
+        if not seg and (lp == 2 or (lp == 0 and B.cols <= dense_w)):
+            # column windows (chosen automatically when B has at most
+            # dense_w columns): every row in Gustavson's order, except rows
+            # of more than 16384 products into one dense window of columns
+            # (product ranges added in range order)
+            ok_rows = ~((B.cols <= dense_w) & (u > 16384))
         else:
             # rows summed in the oracle's order: not split into segments and
             # not spilling out of the level-1 sequence
@@ -298,21 +300,22 @@ def test_one_call_multiply_matches_plan():
     assert list(i2.bin_count) == list(info.bin_count)
 
 
-@pytest.mark.parametrize("seg", [0, 4096])
-def test_options_do_not_change_result(seg):
+@pytest.mark.parametrize("seg,long_path", [(0, 0), (4096, 0), (0, 2)])
+def test_options_do_not_change_result(seg, long_path):
     """Bin thresholds, level-1 size and stage timers change neither the
-    structure nor any value: with the default segments (seg = 0, what the
-    benchmark runs) and with 4096-product segments."""
+    structure nor any value: with the default options (what the benchmark
+    runs), with 4096-product segments and with column windows."""
     A, _ = S.config2(n=8000, cap=300)
-    (rp0, ci0, v0), _ = check(A, A, seg=seg)
-    (rp1, ci1, v1), _ = check(A, A, seg=seg, bin_edges=(16, 48, 100, 300, 700))
-    (rp2, ci2, v2), _ = check(A, A, seg=seg, bin_edges=(8, 16, 32, 64, 128), l1_cap=7168)
+    o = dict(seg=seg, long_path=long_path)
+    (rp0, ci0, v0), _ = check(A, A, **o)
+    (rp1, ci1, v1), _ = check(A, A, bin_edges=(16, 48, 100, 300, 700), **o)
+    (rp2, ci2, v2), _ = check(A, A, bin_edges=(8, 16, 32, 64, 128), l1_cap=7168, **o)
     # stage timers (all, then two) do not change the result
-    (rp4, ci4, v4), _ = check(A, A, seg=seg, timing=1)
-    (rp5, ci5, v5), _ = check(A, A, seg=seg, timing=1, timing_mask=(1 << 8) | (1 << 10))
+    (rp4, ci4, v4), _ = check(A, A, timing=1, **o)
+    (rp5, ci5, v5), _ = check(A, A, timing=1, timing_mask=(1 << 8) | (1 << 10), **o)
     for ci, v in ((ci1, v1), (ci2, v2), (ci4, v4), (ci5, v5)):
         assert np.array_equal(ci, ci0) and np.array_equal(v, v0)
-    if seg:
+    if seg or long_path:
         return
     # a smaller level-1 sequence spills more often: same structure, values
     # within tolerance (checked inside check())
@@ -408,34 +411,38 @@ def test_backward_matches_oracle(dtype, ncols):
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_window_method_row_plans(dtype):
-    """The default method for long rows (column windows), one case per row
-    plan, every value Gustavson's sequential sum: rows of up to 2048
-    products as one sparse window; longer rows partitioned into pieces of
-    2^shift columns -- dense pieces (one accumulator window), sparse pieces
-    in one chunk, and sparse pieces whose products crowd into few columns
-    and overflow one chunk (then swept in dense sub-windows)."""
-    targets = [513, 700, 1500, 2048, 2049, 3000, 5000, 20000, 60000]
+    """Long rows by column windows (long_path 2), one case per row plan,
+    every value Gustavson's sequential sum: rows of up to 1024 products as
+    one sparse window; longer rows partitioned into pieces of 2^shift
+    columns -- pieces of one wavefront's staging, and pieces whose products
+    crowd into few columns and overflow it (then swept by a work-group in
+    dense sub-windows)."""
+    targets = [513, 700, 1024, 1025, 1500, 2048, 2049, 3000, 5000, 20000, 60000]
     A, B = S.crafted_rows(targets * 2, n=60000, dtype=dtype)
-    check(A, B)
+    check(A, B, long_path=2)
     # products crowded into columns [0, 3000) of 60000: overflowing pieces
     A, B = S.crafted_rows([2500, 5000, 9000, 30000], n=60000, col_range=3000, dtype=dtype)
-    check(A, B)
-    # many duplicates in few columns (heapsort path of large buckets)
+    check(A, B, long_path=2)
+    # many duplicates in few columns (large buckets of the counting sort)
     A, B = S.crafted_rows([3000, 5000, 1200], n=60000, col_range=40, dtype=dtype)
-    check(A, B)
+    check(A, B, long_path=2)
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_window_method_dense_rows(dtype):
-    """C with at most 2048 (binary64) / 4096 (binary32) columns: every long
-    row is one dense window; rows above 65536 products are cut into product
-    ranges whose dense partial rows are added in range order (values within
-    tolerance), the others are exact."""
+    """C with at most 2048 (binary64) / 4096 (binary32) columns: column
+    windows are chosen automatically and every long row is one dense window
+    in LDS; rows above 16384 products are cut into product ranges whose
+    dense partial rows are added in range order (values within tolerance),
+    the others are exact.  The merge method (long_path 1) gives the same
+    structure."""
     n, big = (1500, 80000) if dtype == np.float64 else (3500, 120000)
-    A, B = S.crafted_rows([600, 3000, 40000, 70000, big, 513], n=n, dtype=dtype)
+    A, B = S.crafted_rows([600, 3000, 16384, 16385, 40000, 70000, big, 513], n=n, dtype=dtype)
     (rp, ci, v), info = check(A, B, exact=False)
+    (rp1, ci1, v1), _ = check(A, B, exact=False, long_path=1)
+    assert np.array_equal(rp, rp1) and np.array_equal(ci, ci1)
     ref = oracle.spgemm(A.astype(np.float64).as_tuple(), B.astype(np.float64).as_tuple())
-    exact_rows = ref.u <= 65536
+    exact_rows = ref.u <= 16384
     mask = np.repeat(exact_rows, np.diff(ref.row_ptr))
     if dtype == np.float64:
         assert np.array_equal(v[mask], ref.val[mask])
@@ -448,7 +455,7 @@ def test_window_method_matches_segment_method():
     """The two long-row methods give the same structure, and the same values
     wherever both sum in Gustavson's order (workload-2 structure)."""
     A, _ = S.config2(n=30000, cap=5000)
-    (rp0, ci0, v0), i0 = check(A, A)
+    (rp0, ci0, v0), i0 = check(A, A, long_path=2)
     (rp1, ci1, v1), i1 = check(A, A, long_path=1)
     assert np.array_equal(rp0, rp1) and np.array_equal(ci0, ci1)
     assert np.array_equal(v0, v1)
