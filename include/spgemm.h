@@ -223,6 +223,25 @@ int spgemm_compute(spgemm_plan plan, const spgemm_csr *A, const spgemm_csr *B,
 int spgemm_backward(spgemm_plan plan, const spgemm_csr *A, const spgemm_csr *B,
                     const spgemm_csr *C, void *dA_val, void *dB_val, void *stream);
 
+/*
+ * spgemm_backward for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight training loops, harnesses that forbid allocation.
+ * Arguments, results and ordering as for spgemm_backward.  The scratch it
+ * needs lives in a fixed device area of SPGEMM_STATIC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends; nothing is
+ * allocated or freed.  With dB wanted, A's transposed pattern takes
+ * 4 k + 8 (k + 1) + 8 nnz(A) bytes plus a scan area of about k / 128
+ * entries (k = A's columns): SPGEMM_EINVAL when that exceeds the area.  The
+ * products of the dB sums (nnz(hat C) values) are staged beside it when they
+ * fit, else dB is summed without staging (the same products in the same
+ * order, so the same values).  Every call on one GPU uses the same area:
+ * calls that overlap on one GPU (other streams, other host threads) race and
+ * must be ordered by the caller.
+ */
+#define SPGEMM_STATIC_SCRATCH_BYTES (64u << 20)
+int spgemm_backward_static(spgemm_plan plan, const spgemm_csr *A, const spgemm_csr *B,
+                           const spgemm_csr *C, void *dA_val, void *dB_val, void *stream);
+
 /* Fill `info` with the plan's latest statistics. */
 int spgemm_plan_info(spgemm_plan plan, spgemm_info *info);
 

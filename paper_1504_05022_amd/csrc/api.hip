@@ -22,6 +22,11 @@
 
 using namespace spg;
 
+// Fixed device scratch of spgemm_backward_static (one copy per GPU).  Host
+// code never uses the symbol itself as an address: the device address is
+// looked up once per device (static_scratch_ptr) and passed to the kernels.
+static __device__ __align__(256) unsigned char scratch[SPGEMM_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -1059,6 +1064,112 @@ extern "C" int spgemm_backward(spgemm_plan plan, const spgemm_csr *A, const spge
   stage_end(p, SPGEMM_T_BACKWARD, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward");
+  return SPGEMM_OK;
+}
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device (with that device current) and kept.
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;
+
+int static_scratch_ptr(void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (static_cast<int>(g_scratch_ptr.size()) <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SPGEMM_OK;
+}
+
+template <typename T>
+int backward_static_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B,
+                      const spgemm_csr *C, void *dA_val, void *dB_val, void *base,
+                      hipStream_t s) {
+  const bool want_a = dA_val && p->nnzA > 0;
+  const bool want_b = dB_val && p->nnzB > 0;
+  if (!want_a && !want_b) return SPGEMM_OK;
+  const T *aval = static_cast<const T *>(A->val);
+  const T *bval = static_cast<const T *>(B->val);
+  const T *dc = static_cast<const T *>(C->val);
+  T *dA = want_a ? static_cast<T *>(dA_val) : nullptr;
+  T *dB = want_b ? static_cast<T *>(dB_val) : nullptr;
+  if (!want_b) {
+    launch_grad_entries<T>(A->row_ptr, A->col_idx, aval, p->m, p->nnzA, p->P, B->row_ptr,
+                           B->col_idx, bval, p->n, C->row_ptr, C->col_idx, dc, dA, nullptr, s);
+    return SPGEMM_OK;
+  }
+  // A's transposed pattern, then the staged dB products if they fit too
+  Layout L;
+  const size_t oc = L.add<int32_t>(p->k);
+  const size_t ot = L.add<int64_t>(p->k + 1);
+  const size_t orr = L.add<int32_t>(p->nnzA);
+  const size_t op = L.add<int32_t>(p->nnzA);
+  const size_t opa = L.add<int64_t>(scan_part_len(std::max<int64_t>(p->k, 1)));
+  if (L.bytes() > SPGEMM_STATIC_SCRATCH_BYTES)
+    return fail(SPGEMM_EINVAL, "A's transposed pattern needs " + std::to_string(L.bytes()) +
+                                   " bytes, more than the static scratch (" +
+                                   std::to_string(SPGEMM_STATIC_SCRATCH_BYTES) + " bytes)");
+  const int64_t nprod = p->info.nnz_hat;
+  const size_t ow = L.add<T>(nprod > 0 ? nprod : 0);
+  T *W = (nprod > 0 && L.bytes() <= SPGEMM_STATIC_SCRATCH_BYTES) ? at<T>(base, ow) : nullptr;
+  int32_t *cnt = at<int32_t>(base, oc);
+  int64_t *tptr = at<int64_t>(base, ot);
+  int32_t *trow = at<int32_t>(base, orr);
+  int32_t *tpos = at<int32_t>(base, op);
+  int64_t *tpart = at<int64_t>(base, opa);
+  // rebuilt on every call: another call may have used the area since
+  launch_transpose_pattern(A->row_ptr, A->col_idx, p->m, p->k, p->nnzA, cnt, tptr, trow, tpos,
+                           tpart, s);
+  if (want_a || W)
+    launch_grad_entries<T>(A->row_ptr, A->col_idx, aval, p->m, p->nnzA, p->P, B->row_ptr,
+                           B->col_idx, bval, p->n, C->row_ptr, C->col_idx, dc, dA, W, s);
+  if (W)
+    launch_grad_b_sum<T>(tptr, tpos, p->P, B->row_ptr, p->k, W, dB, s);
+  else
+    launch_grad_b<T>(tptr, trow, tpos, aval, B->row_ptr, B->col_idx, p->k, C->row_ptr,
+                     C->col_idx, dc, dB, s);
+  return SPGEMM_OK;
+}
+
+}  // namespace
+
+extern "C" int spgemm_backward_static(spgemm_plan plan, const spgemm_csr *A,
+                                      const spgemm_csr *B, const spgemm_csr *C, void *dA_val,
+                                      void *dB_val, void *stream) {
+  if (!plan) return fail(SPGEMM_EINVAL, "plan is NULL");
+  int rc;
+  if ((rc = check_csr(A, "A")) != SPGEMM_OK) return rc;
+  if ((rc = check_csr(B, "B")) != SPGEMM_OK) return rc;
+  if ((rc = check_csr(C, "C")) != SPGEMM_OK) return rc;
+  spgemm_plan p = plan;
+  if (A->rows != p->m || A->cols != p->k || B->cols != p->n || A->nnz != p->nnzA ||
+      B->nnz != p->nnzB || A->row_ptr != p->arp || A->col_idx != p->acol ||
+      B->row_ptr != p->brp || B->col_idx != p->bcol || A->dtype != p->dtype ||
+      B->dtype != p->dtype)
+    return fail(SPGEMM_ESTATE, "A/B differ from the analyzed matrices");
+  if (C->rows != p->m || C->cols != p->n || C->dtype != p->dtype)
+    return fail(SPGEMM_EINVAL, "C must be the m x n result of this plan, with A's dtype");
+  if (p->info.nnz_c >= 0 && C->nnz != p->info.nnz_c)
+    return fail(SPGEMM_EINVAL, "C has a different nnz than the computed product");
+  void *base = nullptr;
+  if ((rc = static_scratch_ptr(&base)) != SPGEMM_OK) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  p->stream = s;
+  stage_begin(p, SPGEMM_T_BACKWARD, s);
+  rc = p->dtype == SPGEMM_F64
+           ? backward_static_t<double>(p, A, B, C, dA_val, dB_val, base, s)
+           : backward_static_t<float>(p, A, B, C, dA_val, dB_val, base, s);
+  if (rc != SPGEMM_OK) return rc;
+  stage_end(p, SPGEMM_T_BACKWARD, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "backward_static");
   return SPGEMM_OK;
 }
 

@@ -84,7 +84,8 @@ class BatchStats(ctypes.Structure):
 
 # exported symbols declared in include/spgemm.h
 EXPORTS = ("spgemm_default_options", "spgemm_strerror", "spgemm_last_error", "spgemm_analyze",
-           "spgemm_compute", "spgemm_backward", "spgemm_plan_info", "spgemm_plan_destroy",
+           "spgemm_compute", "spgemm_backward", "spgemm_backward_static", "spgemm_plan_info",
+           "spgemm_plan_destroy",
            "spgemm_batch_create", "spgemm_batch_run", "spgemm_batch_stats_get",
            "spgemm_batch_destroy", "spgemm_merge_pairs", "spgemm_multiply")
 
@@ -139,6 +140,9 @@ def load(path: str = LIB_PATH):
     lib.spgemm_backward.argtypes = [P, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc),
                                     ctypes.POINTER(CsrDesc), P, P, P]
     lib.spgemm_backward.restype = ctypes.c_int
+    lib.spgemm_backward_static.argtypes = [P, ctypes.POINTER(CsrDesc), ctypes.POINTER(CsrDesc),
+                                           ctypes.POINTER(CsrDesc), P, P, P]
+    lib.spgemm_backward_static.restype = ctypes.c_int
     lib.spgemm_plan_info.argtypes = [P, ctypes.POINTER(Info)]
     lib.spgemm_plan_info.restype = ctypes.c_int
     lib.spgemm_plan_destroy.argtypes = [P]
@@ -284,6 +288,18 @@ class Plan:
         rc = _lib.spgemm_backward(self._h, ctypes.byref(self._da), ctypes.byref(self._db),
                                   ctypes.byref(dc), dA.data_ptr() if want_a else None,
                                   dB.data_ptr() if want_b else None, _stream_handle())
+        _check(rc)
+        return dA, dB
+
+    def backward_static(self, C: CsrMatrix, dC: torch.Tensor, dA=None, dB=None):
+        """backward() through the entry point that allocates no device memory
+        (its scratch is a fixed area in the library): the caller passes the
+        output tensors dA / dB (None to skip one)."""
+        dc = C.with_values(dC.contiguous()).desc()
+        rc = _lib.spgemm_backward_static(self._h, ctypes.byref(self._da), ctypes.byref(self._db),
+                                         ctypes.byref(dc), dA.data_ptr() if dA is not None else None,
+                                         dB.data_ptr() if dB is not None else None,
+                                         _stream_handle())
         _check(rc)
         return dA, dB
 
