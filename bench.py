@@ -93,11 +93,23 @@ def copy_probe(mib):
                       "launches": 4}), flush=True)
 
 
-# files the long-row kernels are compiled from: counter figures stay valid
-# only while these are unchanged
-KERNEL_SOURCES = ("paper_1504_05022_amd/csrc/long.hip", "paper_1504_05022_amd/csrc/window.hip",
-                  "paper_1504_05022_amd/csrc/common.hpp", "paper_1504_05022_amd/csrc/internal.hpp",
-                  "include/spgemm.h")
+# files the long-row kernels of each method are compiled from: counter
+# figures stay valid only while these are unchanged
+_CSRC = "paper_1504_05022_amd/csrc/"
+KERNEL_SOURCES = {
+    "merge": (_CSRC + "long.hip", _CSRC + "common.hpp", _CSRC + "internal.hpp", _CSRC + "radix.hpp",
+              "include/spgemm.h"),
+    "window": (_CSRC + "window.hip", _CSRC + "common.hpp", _CSRC + "internal.hpp",
+               "include/spgemm.h"),
+}
+
+
+def source_sha1(method):
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES[method]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
 
 
 def counters_file(kernel):
@@ -105,21 +117,17 @@ def counters_file(kernel):
     return os.path.join(ROOT, "profiles", "%s_irregular_AxA_200k_hbm_counters.md" % kernel.split()[0])
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, method):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (two rocprofv3 passes, calibrated on a plain copy), or None when there is
     none for this kernel or its sources changed since it was taken."""
-    import hashlib
     try:
         kv = {}
         for line in open(counters_file(kernel)):
             if ":" in line and not line.startswith(("#", "|", " ")):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        h = hashlib.sha1()
-        for f in KERNEL_SOURCES:
-            h.update(open(os.path.join(ROOT, f), "rb").read())
-        if kv.get("source_sha1") != h.hexdigest() or not kernel.startswith(kv["traffic_kernel"]):
+        if kv.get("source_sha1") != source_sha1(method) or not kernel.startswith(kv["traffic_kernel"]):
             return None
         return int(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -593,7 +601,8 @@ def main():
 
     # dominant kernel: the longest of the long-row kernels of the method the
     # library takes for this product
-    if A.cols <= dense_cols(s):
+    method = "window" if A.cols <= dense_cols(s) else "merge"
+    if method == "window":
         part_b, sym_b, num_b = window_kernel_bytes(A, A, crp, s)
         cand = [("k_wpart (partition of long-row segments into column pieces)", part_b,
                  stages["long_wave"]),
@@ -636,7 +645,7 @@ def main():
         "stage_ms": breakdown,
         "roofline": {"kernel": name, "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(name),
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(name, method),
                      "algorithmic_bytes": int(kbytes), "kernel_ms": round(kms, 4)},
     }
     out["memory"] = memory_accounting(A, crp, info, s)

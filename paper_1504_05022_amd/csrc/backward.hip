@@ -59,6 +59,7 @@ __global__ __launch_bounds__(256) void k_grad_b(const int64_t *tptr, const int32
 // those of the definition (and of k_grad_b).
 constexpr int BW_CH = 1024;
 constexpr int BW_NT = 256;
+constexpr int BW_U = 8;  // entries of b_j* whose loads are in flight together
 constexpr int BW_MAP_BYTES = 16384;  // dense dC row per wavefront
 
 template <typename T> constexpr int bw_map_cols() { return BW_MAP_BYTES / static_cast<int>(sizeof(T)); }
@@ -106,18 +107,32 @@ __global__ __launch_bounds__(BW_NT) void k_grad_entries(
       T *wp = W ? W + (P[ee] - q0) : nullptr;
       T s = T(0);
       int32_t from = c0;
-      for (int32_t q = q0; q < q1; ++q) {
-        const int32_t k = bcol[q];
-        T y;
-        if (DENSE) {
-          y = mp[k];
-        } else {
-          const int32_t pc = find_col(ccol, from, c1, k);
-          y = dc[pc];
-          from = pc + 1;  // columns of b_j* ascend
+      // blocks of BW_U entries of b_j*: their loads are issued together
+      // (clamped to the row), then the block is added in order
+      for (int32_t qb = q0; qb < q1; qb += BW_U) {
+        int32_t kk[BW_U];
+        T bv[BW_U];
+#pragma unroll
+        for (int u = 0; u < BW_U; ++u) {
+          const int32_t q = qb + u < q1 ? qb + u : q1 - 1;
+          kk[u] = bcol[q];
+          bv[u] = bval[q];
         }
-        s = s + y * bval[q];
-        if (wp) wp[q] = av * y;
+#pragma unroll
+        for (int u = 0; u < BW_U; ++u) {
+          if (qb + u < q1) {
+            T y;
+            if (DENSE) {
+              y = mp[kk[u]];
+            } else {
+              const int32_t pc = find_col(ccol, from, c1, kk[u]);
+              y = dc[pc];
+              from = pc + 1;  // columns of b_j* ascend
+            }
+            s = s + y * bv[u];
+            if (wp) wp[qb + u] = av * y;
+          }
+        }
       }
       if (dA) dA[ee] = s;
     }
@@ -141,7 +156,19 @@ __global__ __launch_bounds__(256) void k_grad_b_sum(const int64_t *tptr, const i
   const int32_t q0 = brp[j], q1 = brp[j + 1];
   for (int32_t q = q0 + lane(); q < q1; q += WAVE) {
     T s = T(0);
-    for (int64_t d = t0; d < t1; ++d) s = s + W[P[tpos[d]] + (q - q0)];
+    // blocks of BW_U entries of A's column j: offsets, then products, each
+    // loaded together (clamped to the column), then added in order
+    for (int64_t db = t0; db < t1; db += BW_U) {
+      int64_t off[BW_U];
+#pragma unroll
+      for (int u = 0; u < BW_U; ++u) off[u] = P[tpos[db + u < t1 ? db + u : t1 - 1]];
+      T v[BW_U];
+#pragma unroll
+      for (int u = 0; u < BW_U; ++u) v[u] = W[off[u] + (q - q0)];
+#pragma unroll
+      for (int u = 0; u < BW_U; ++u)
+        if (db + u < t1) s = s + v[u];
+    }
     dB[q] = s;
   }
 }

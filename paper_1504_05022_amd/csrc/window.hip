@@ -669,27 +669,40 @@ template <typename T, bool NUM> struct DenseLds {
   alignas(16) uint32_t hit[NUM ? 4 : DW / 4];  // symbolic: one byte per column
 };
 
-// Wavefronts per SIMD the dense kernels' registers are held to (the LDS
-// allows about 2.5 numeric, 16 KB accumulator, and 9 symbolic).
+// Wavefronts per work-group of the dense kernels (numeric ones may share
+// one accumulator between NWV wavefronts, each owning every NWV-th block of
+// 32 columns: measured slower at 2 than at 1, as every wavefront gathers
+// every product), and wavefronts per SIMD their registers are held to (the
+// LDS allows about 2.5 numeric ones, 16 KB accumulator, and 9 symbolic).
+template <bool NUM> constexpr int dense_nwv() { return 1; }
 template <bool NUM> constexpr int dense_waves_per_simd() { return NUM ? 2 : 5; }
 
-// One wavefront per item (the hardware deals new wavefronts to CUs as
+// One work-group per item (the hardware deals new work-groups to CUs as
 // others finish, which balances items of very different sizes; a shared
-// item counter would serialize the wavefronts on one address).
+// item counter would serialize them on one address).
 // Symbolic (NUM false): the item's columns counted (one-range items) or
 // kept as a bitmap for the reduction (product ranges).  Numeric: the row
 // written to C in column order (one-range items) or the dense partial row
 // of the range.
 template <typename T, bool NUM>
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(dense_waves_per_simd<NUM>())))
+__global__ __launch_bounds__(WAVE * dense_nwv<NUM>())
+__attribute__((amdgpu_waves_per_eu(dense_waves_per_simd<NUM>())))
 void k_wdense(WinArgsW<T> a, uint32_t *dbits, T *dacc) {
   constexpr int G = GE;  // entries per load group
+  constexpr int NWV = dense_nwv<NUM>();
   __shared__ DenseLds<T, NUM> L;
   const int ln = lane();
+  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / WAVE));
   const int n = static_cast<int>(a.n);
   if (a.n > DenseLds<T, NUM>::DW) return;  // launched only for n <= DW
   const int64_t it = xcd_block_id<16>();
   if (it >= a.nitems) return;
+  auto group_sync = [&]() {
+    if (NWV > 1)
+      __syncthreads();
+    else
+      wave_sync();
+  };
   const int nwords = (n + 31) >> 5;
   const int nhit = (n + 3) >> 2;
   uint8_t *hit = reinterpret_cast<uint8_t *>(L.hit);
@@ -703,18 +716,22 @@ void k_wdense(WinArgsW<T> a, uint32_t *dbits, T *dacc) {
     if (sizeof(T) == 4) v.y = v.z = v.w = v.x;
     else { v.z = v.x; v.w = v.y; }
     uint4 *dst = reinterpret_cast<uint4 *>(L.acc);
-    for (int q = ln; q < (n + PER - 1) / PER; q += WAVE) dst[q] = v;
+    for (int q = threadIdx.x; q < (n + PER - 1) / PER; q += WAVE * NWV) dst[q] = v;
   } else {
     uint4 *dst = reinterpret_cast<uint4 *>(L.hit);
     for (int q = ln; q < (n + 15) / 16; q += WAVE) dst[q] = make_uint4(0u, 0u, 0u, 0u);
   }
-  wave_sync();
+  group_sync();
   const GLOBAL_AS int32_t *bcol = as_global(a.e.bcol);
   const GLOBAL_AS T *bval = as_global(a.e.bval);
+  // numeric: wavefront wv owns the columns with (c / 32) % NWV == wv, so
+  // the wavefronts of a work-group never touch one column
   auto update = [&](int32_t c, T p) {
     if (NUM) {
-      const T o = L.acc[c];
-      L.acc[c] = (untouched(o) ? T(0) : o) + p;
+      if (((c >> 5) & (NWV - 1)) == wv) {
+        const T o = L.acc[c];
+        L.acc[c] = (untouched(o) ? T(0) : o) + p;
+      }
     } else {
       hit[c] = 1;
     }
@@ -786,12 +803,12 @@ void k_wdense(WinArgsW<T> a, uint32_t *dbits, T *dacc) {
       }
       if (a.e.P[eb + nb] - P0 >= q1) break;
     }
-    wave_sync();
+    group_sync();
     if (wr.nitem > 1) {
       // one range of a row cut into product ranges
       if (NUM) {
         T *dst = dacc + (wr.dslot0 + w.k) * static_cast<int64_t>(n);
-        for (int c = ln; c < n; c += WAVE) {
+        for (int c = threadIdx.x; c < n; c += WAVE * NWV) {
           const T v = L.acc[c];
           dst[c] = untouched(v) ? T(0) : v;
         }
@@ -810,7 +827,7 @@ void k_wdense(WinArgsW<T> a, uint32_t *dbits, T *dacc) {
       for (int q = ln; q < nhit; q += WAVE) c += __popc(L.hit[q] & 0x01010101u);
       c = __shfl(static_cast<long long>(group_incl_sum<WAVE>(c)), WAVE - 1, WAVE);
       if (ln == 0) a.cnt[it] = c;
-    } else {
+    } else if (wv == 0) {
       // the row in column order (lanes on consecutive columns, coalesced
       // stores); eight columns per lane read ahead
       int32_t *dcol = a.c_col + a.rowoff[wr.row];
@@ -1377,8 +1394,8 @@ void win_numeric(const EscArgs<T> &e, int64_t n, const WinRow *rows, const WinWo
   a.c_col = c_col;
   a.c_val = c_val;
   if (n <= (int64_t(1) << ValTraits<T>::dl)) {
-    hipLaunchKernelGGL((k_wdense<T, true>), dim3(nitems), dim3(WAVE), 0, s, a,
-                       static_cast<uint32_t *>(nullptr), dacc);
+    hipLaunchKernelGGL((k_wdense<T, true>), dim3(nitems), dim3(WAVE * dense_nwv<true>()), 0, s,
+                       a, static_cast<uint32_t *>(nullptr), dacc);
     if (nslots > 0)
       hipLaunchKernelGGL((k_wnum_reduce<T>), dim3(nslots * ((n + WNT - 1) / WNT)), dim3(WNT), 0, s,
                          rows, slot_row, nslots, n, dbits, dacc, rowoff, c_col, c_val);
