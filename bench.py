@@ -237,19 +237,22 @@ def window_kernel_bytes(A, B, crp, s):
     return part, sym, num
 
 
-def memory_accounting(A, crp, info, s):
-    """Temporary storage of the product under the three allocation schemes
+def row_upper_bounds(A, B):
+    """u_i = sum over the entries a_ij of nnz(b_j*) (Algorithm 2), on the host."""
+    deg = np.diff(A.row_ptr.astype(np.int64))
+    bdeg = np.diff(B.row_ptr.astype(np.int64))
+    return np.bincount(np.repeat(np.arange(A.rows), deg), weights=bdeg[A.col_idx],
+                       minlength=A.rows).astype(np.int64)
+
+
+def memory_accounting(u, crp, info, s, long_min=LONG_MIN):
+    """Temporary storage of one product under the three allocation schemes
     the paper compares (precise nnz(c_i); hybrid: the Algorithm 3 sizes plus
     2x growth of a long row's 256-entry slot until its result fits; upper
-    bound u_i), in MB of (column, value) entries, next to the device scratch
-    this implementation held (analysis + C~ + long-row space + pool)."""
-    arp = A.row_ptr.astype(np.int64)
-    deg = np.diff(arp)
-    u = np.bincount(np.repeat(np.arange(A.rows), deg), weights=deg[A.col_idx],
-                    minlength=A.rows).astype(np.int64)
+    bound u_i), in MB of (column, value) entries, next to the device memory
+    this implementation's plan held after the product (spgemm_info)."""
     cn = np.diff(crp.astype(np.int64))
-    long_rows = u > LONG_MIN
-    grow = cn[long_rows]
+    grow = cn[u > long_min]
     cap = np.where(grow > 256, 256 * 2.0 ** np.ceil(np.log2(np.maximum(grow, 1) / 256.0)), 0)
     mb = (4 + s) / 1e6
     precise = int(cn.sum())
@@ -260,6 +263,47 @@ def memory_accounting(A, crp, info, s):
             "hybrid_over_precise": round(hybrid / max(precise, 1), 3),
             "upper_over_precise": round(upper / max(precise, 1), 3),
             "this_implementation_scratch_MB": round(int(info.bytes_scratch) / 1e6, 1)}
+
+
+def memory_table(torch, S, L):
+    """Memory of the three allocation schemes and of this implementation for
+    workloads 1, 3 (both products of R(AP)), 4 (summed over its problems) and
+    5; workload 2 is reported with the headline."""
+    def one(A, B):
+        dA, dB = L.CsrMatrix.from_host(A), L.CsrMatrix.from_host(B)
+        plan = L.Plan(dA, dB)
+        C = plan.compute()
+        torch.cuda.synchronize()
+        crp = C.row_ptr.cpu().numpy()
+        info = plan.info
+        plan.close()
+        del C, dA, dB
+        return memory_accounting(row_upper_bounds(A, B), crp, info, A.val.dtype.itemsize)
+
+    def add(rows):
+        keys = ("precise_MB", "hybrid_MB", "upper_bound_MB", "this_implementation_scratch_MB")
+        t = {k: round(sum(r[k] for r in rows), 1) for k in keys}
+        t["hybrid_over_precise"] = round(t["hybrid_MB"] / max(t["precise_MB"], 1e-9), 3)
+        t["upper_over_precise"] = round(t["upper_bound_MB"] / max(t["precise_MB"], 1e-9), 3)
+        return t
+
+    out = {}
+    A1, _ = S.config1()
+    out["workload1_AxA_2000"] = one(A1, A1)
+    A3, P3, R3 = S.config3()
+    AP = S.Csr(*gpu_product(torch, L, A3, P3))
+    out["workload3_AxP"] = one(A3, P3)
+    out["workload3_Rx(AP)"] = one(R3, AP)
+    out["workload4_512_problems"] = add([one(a, b) for a, b in S.config4()])
+    A5, B5 = S.config5()
+    out["workload5_AxB"] = one(A5, B5)
+    return out
+
+
+def gpu_product(torch, L, A, B):
+    """A*B on the GPU (this library), as a host CSR tuple."""
+    C = L.spgemm(L.CsrMatrix.from_host(A), L.CsrMatrix.from_host(B))
+    return C.to_host()
 
 
 def extensions(args, torch, S, L):
@@ -294,12 +338,28 @@ def extensions(args, torch, S, L):
             del C
         torch.cuda.synchronize()
         pms = (time.perf_counter() - t0) * 1e3
-        del dev
+        # ... and with plans analyzed beforehand (only compute() timed), the
+        # fair comparison with a batch whose structure was set up at create
+        plans = [L.Plan(a_, b_) for a_, b_ in dev]
+        for pl in plans[:8]:
+            pl.compute()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for pl in plans:
+            C = pl.compute()
+            del C
+        torch.cuda.synchronize()
+        cms = (time.perf_counter() - t0) * 1e3
+        for pl in plans:
+            pl.close()
+        del plans, dev
         out["batched"] = {
             "workload": "512 banded problems, n log-uniform in [1024, 65536], 4-32 nnz/row "
                         "in a 5% band, FP64 even / FP32 odd",
             "ms_per_run": round(bms, 3), "gflops": round(st["flops"] / (bms * 1e-3) / 1e9, 2),
             "plain_sequential_ms": round(pms, 3),
+            "plain_compute_reused_plans_ms": round(cms, 3),
+            "speedup_vs_compute_reused_plans": round(cms / bms, 3),
             "plain_gflops": round(st["flops"] / (pms * 1e-3) / 1e9, 2),
             "speedup_vs_plain": round(pms / bms, 3), "flops": st["flops"], "nnz_c": st["nnz_c"],
             "fallback": st["fallback"], "bin_edges": st["bin_edges"],
@@ -329,9 +389,13 @@ def extensions(args, torch, S, L):
         bwms = (time.perf_counter() - t0) * 1e3 / reps
         fl = int(plan.info.flops)
         plan.close()
+        # per-stage breakdown of the forward (every stage timer on)
+        _, finfo = L.spgemm(dA, dB, return_info=True, timing=1)
+        fstages = {k: round(float(v), 4) for k, v in zip(L.STAGES, finfo.stage_ms) if v > 0}
         out["backward"] = {
             "workload": "A 500000^2 power law (2.2, mean 20) x B 500000x4096 (32/row), FP32 N(0,1)",
             "forward_ms": round(fms, 3), "forward_gflops": round(fl / (fms * 1e-3) / 1e9, 2),
+            "forward_stage_ms": fstages,
             "backward_ms": round(bwms, 3),
             "backward_gflops": round(2 * fl / (bwms * 1e-3) / 1e9, 2),
             "backward_over_forward": round(bwms / fms, 3), "flops_forward": fl}
@@ -349,6 +413,12 @@ def extensions(args, torch, S, L):
         out["galerkin"] = galerkin_orders(torch, S, L, reps)
     except Exception as e:
         out["galerkin"] = {"error": repr(e)[:300]}
+    torch.cuda.empty_cache()
+    # ---- memory of the allocation schemes (Section 4), workloads 1, 3, 4, 5
+    try:
+        out["memory_workloads"] = memory_table(torch, S, L)
+    except Exception as e:
+        out["memory_workloads"] = {"error": repr(e)[:300]}
     return out
 
 
@@ -648,7 +718,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(name, method),
                      "algorithmic_bytes": int(kbytes), "kernel_ms": round(kms, 4)},
     }
-    out["memory"] = memory_accounting(A, crp, info, s)
+    out["memory"] = memory_accounting(row_upper_bounds(A, A), crp, info, s)
     if not args.no_cpu:
         import oracle
         # the oracle as it stands, single thread, on the whole workload,

@@ -163,7 +163,11 @@ typedef struct {
   int64_t max_u;
   int64_t bin_count[SPGEMM_NBINS];
   int64_t long_items;   /* long-row work items after splitting               */
-  int64_t bytes_scratch;/* device scratch held by the plan                   */
+  int64_t bytes_scratch;/* most device memory the plan held at once during
+                           the latest call, as requested from the allocator:
+                           analysis arrays, C~ with the long-row tables and
+                           pool (compute), A's transposed pattern and the
+                           staged products (backward); C itself excluded    */
   int64_t pool_entries; /* long-row pool capacity at the end of compute      */
   int64_t pool_used;    /* entries taken from the pool                       */
   int32_t realloc_rounds; /* pool exhaustions handled by relaunching         */

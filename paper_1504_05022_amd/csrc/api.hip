@@ -47,13 +47,19 @@ int hip_fail(hipError_t e, const char *what) {
     if (_e != hipSuccess) return hip_fail(_e, #expr);   \
   } while (0)
 
+// Bytes requested from the allocator for a buffer of `bytes` (multiples of
+// 256, at least 256).
+inline size_t alloc_size(size_t bytes) {
+  bytes = (bytes + 255) & ~static_cast<size_t>(255);
+  return bytes == 0 ? 256 : bytes;
+}
+
 struct Allocator {
   spgemm_alloc_fn af = nullptr;
   spgemm_free_fn ff = nullptr;
   void *ctx = nullptr;
   void *get(size_t bytes, hipStream_t s) const {
-    bytes = (bytes + 255) & ~static_cast<size_t>(255);
-    if (bytes == 0) bytes = 256;
+    bytes = alloc_size(bytes);
     if (af) return af(bytes, ctx, reinterpret_cast<void *>(s));
     void *p = nullptr;
     if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
@@ -194,9 +200,11 @@ struct spgemm_plan_s {
   void *cws = nullptr;
   size_t cws_bytes = 0;
   std::vector<void *> pool_chunks;
+  size_t pool_bytes = 0;  // allocated for pool_chunks
 
   // backward scratch: A's transposed pattern, built on first use
   void *bws = nullptr;
+  size_t bws_bytes = 0;
   int32_t *tcnt = nullptr, *trow = nullptr, *tpos = nullptr;
   int64_t *tptr = nullptr, *tpart = nullptr;
 
@@ -276,6 +284,19 @@ void release_compute(spgemm_plan p, hipStream_t s) {
   p->cws_bytes = 0;
   for (void *c : p->pool_chunks) p->al.put(c, s);
   p->pool_chunks.clear();
+  p->pool_bytes = 0;
+}
+
+// Device memory the plan holds now, as requested from the allocator
+// (analysis, C~ and long-row tables, pool chunks, A's transposed pattern).
+// At the end of compute (C~ still held, released on return) this is the
+// call's peak apart from C itself.
+int64_t held_bytes(spgemm_plan p) {
+  size_t b = p->pool_bytes;
+  if (p->ws) b += alloc_size(p->ws_bytes);
+  if (p->cws) b += alloc_size(p->cws_bytes);
+  if (p->bws) b += alloc_size(p->bws_bytes);
+  return static_cast<int64_t>(b);
 }
 
 void destroy_plan(spgemm_plan p) {
@@ -499,7 +520,7 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   I.max_u = static_cast<int64_t>(S.max_u);
   for (int b = 0; b < NBINS; ++b) I.bin_count[b] = S.bin_off[b + 1] - S.bin_off[b];
   I.long_items = S.n_items;
-  I.bytes_scratch = static_cast<int64_t>(p->ws_bytes);
+  I.bytes_scratch = held_bytes(p);
   for (int st : {SPGEMM_T_UPPER, SPGEMM_T_BIN})
     if (timed(p, st)) (void)hipEventElapsedTime(&I.stage_ms[st], p->ev[2 * st], p->ev[2 * st + 1]);
   if (info) *info = I;
@@ -705,6 +726,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     void *chunk = p->al.get(pool_chunk_bytes(entries, sizeof(T)), s);
     if (!chunk) return fail(SPGEMM_ENOMEM, "long-row pool allocation failed");
     p->pool_chunks.push_back(chunk);
+    p->pool_bytes += alloc_size(pool_chunk_bytes(entries, sizeof(T)));
     *p->hpool = pool_view(chunk, entries);
     p->hpool->used = used;
     launch_set_pool(p->dpool, *p->hpool, s);
@@ -849,10 +871,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   I.pool_used = legacy ? static_cast<int64_t>(p->hstat->pool_used) : 0;
   I.long_items = use_win ? S.w_items : (nlong > 0 ? S.n_items : 0);
   I.pool_entries = pool_entries;
-  // device scratch held now: analysis, C~ and long-row tables, pool chunks
-  I.bytes_scratch = static_cast<int64_t>(p->ws_bytes + p->cws_bytes);
-  for (int64_t e = pool_entries, k = 0; k <= I.realloc_rounds && legacy; ++k, e /= 2)
-    I.bytes_scratch += static_cast<int64_t>(pool_chunk_bytes(e, sizeof(T)));
+  I.bytes_scratch = held_bytes(p);
 
   // ---- stage 4b: allocate C and copy C~ into it
   void *crp = crp_guard.p;
@@ -989,12 +1008,13 @@ int ensure_transpose(spgemm_plan p, const spgemm_csr *A, hipStream_t s) {
   const size_t opa = L.add<int64_t>(scan_part_len(std::max<int64_t>(p->k, 1)));
   p->bws = p->al.get(L.bytes(), s);
   if (!p->bws) return fail(SPGEMM_ENOMEM, "backward scratch allocation failed");
+  p->bws_bytes = L.bytes();
   p->tcnt = at<int32_t>(p->bws, oc);
   p->tptr = at<int64_t>(p->bws, ot);
   p->trow = at<int32_t>(p->bws, orr);
   p->tpos = at<int32_t>(p->bws, op);
   p->tpart = at<int64_t>(p->bws, opa);
-  p->info.bytes_scratch += static_cast<int64_t>(L.bytes());
+  p->info.bytes_scratch = held_bytes(p);
   launch_transpose_pattern(A->row_ptr, A->col_idx, p->m, p->k, p->nnzA, p->tcnt, p->tptr,
                            p->trow, p->tpos, p->tpart, s);
   return SPGEMM_OK;
@@ -1021,6 +1041,9 @@ int backward_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, const sp
   T *W = nullptr;
   if (want_b && nprod > 0 && nprod * static_cast<int64_t>(sizeof(T)) <= kMaxStagedProducts)
     W = static_cast<T *>(p->al.get(static_cast<size_t>(nprod) * sizeof(T), s));
+  // the call's peak: what the plan holds plus the staged products
+  p->info.bytes_scratch =
+      held_bytes(p) + (W ? static_cast<int64_t>(alloc_size(static_cast<size_t>(nprod) * sizeof(T))) : 0);
   if (want_a || W)
     launch_grad_entries<T>(A->row_ptr, A->col_idx, aval, p->m, p->nnzA, p->P, B->row_ptr,
                            B->col_idx, bval, p->n, C->row_ptr, C->col_idx, dc, dA, W, s);
