@@ -128,7 +128,12 @@ typedef struct {
                            2 = column windows: each long row is cut into
                              windows of columns, sized by a symbolic pass
                              and written straight into C                     */
-  int32_t pad_;
+  int32_t long_direct;  /* merge method only: 0 = results of split long rows
+                           go to a range buffer of u_i entries per row and
+                           are copied into C (default, faster); 1 = a
+                           counting pass sizes them first and they are
+                           written straight into C (no range buffer: less
+                           device memory, about 5% slower on workload 2)   */
 } spgemm_options;
 
 #define SPGEMM_NBINS 38

@@ -208,6 +208,11 @@ struct spgemm_plan_s {
   int32_t *tcnt = nullptr, *trow = nullptr, *tpos = nullptr;
   int64_t *tptr = nullptr, *tpart = nullptr;
 
+  // second stream for the short-row kernels (from a per-device pool) and
+  // the events that fork it from and join it to the caller's stream
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+
   spgemm_info info{};
   hipEvent_t ev[2 * SPGEMM_NSTAGES] = {};
   bool events = false;
@@ -278,6 +283,60 @@ void give_event(int dev, hipEvent_t e) {
   g_ev_free.emplace_back(dev, e);
 }
 
+// Auxiliary streams outlive plans too (one is taken per plan that computes
+// and returned when the plan is destroyed); default priority, not
+// synchronized with the null stream.
+std::vector<std::pair<int, hipStream_t>> g_aux_free;
+
+hipError_t take_aux(int dev, hipStream_t *st) {
+  {
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    for (size_t i = g_aux_free.size(); i-- > 0;) {
+      if (g_aux_free[i].first == dev) {
+        *st = g_aux_free[i].second;
+        g_aux_free.erase(g_aux_free.begin() + static_cast<std::ptrdiff_t>(i));
+        return hipSuccess;
+      }
+    }
+  }
+  return hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+}
+
+void give_aux(int dev, hipStream_t st) {
+  if (!st) return;
+  std::lock_guard<std::mutex> lk(g_ev_mu);
+  g_aux_free.emplace_back(dev, st);
+}
+
+// Forks the plan's auxiliary stream from `s` (its work then follows
+// everything enqueued on `s` so far).  False when no stream or event could
+// be had: the caller then stays on `s`.
+bool fork_aux(spgemm_plan p, hipStream_t s) {
+  if (!p->aux) {
+    hipStream_t st = nullptr;
+    if (take_aux(p->dev, &st) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    p->aux = st;
+  }
+  if (!p->fork_ev && take_event(p->dev, &p->fork_ev) != hipSuccess) p->fork_ev = nullptr;
+  if (!p->join_ev && take_event(p->dev, &p->join_ev) != hipSuccess) p->join_ev = nullptr;
+  if (!p->fork_ev || !p->join_ev) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return hipEventRecord(p->fork_ev, s) == hipSuccess &&
+         hipStreamWaitEvent(p->aux, p->fork_ev, 0) == hipSuccess;
+}
+
+// Makes `s` wait for everything enqueued on the auxiliary stream.
+void join_aux(spgemm_plan p, hipStream_t s) {
+  if (!p->aux || !p->join_ev) return;
+  (void)hipEventRecord(p->join_ev, p->aux);
+  (void)hipStreamWaitEvent(s, p->join_ev, 0);
+}
+
 void release_compute(spgemm_plan p, hipStream_t s) {
   p->al.put(p->cws, s);
   p->cws = nullptr;
@@ -306,6 +365,9 @@ void destroy_plan(spgemm_plan p) {
   p->al.put(p->bws, p->stream);
   if (p->events)
     for (auto &e : p->ev) give_event(p->dev, e);
+  give_event(p->dev, p->fork_ev);
+  give_event(p->dev, p->join_ev);
+  give_aux(p->dev, p->aux);
   delete p;
 }
 
@@ -322,6 +384,7 @@ int check_options(const spgemm_options &o) {
     return fail(SPGEMM_EINVAL, "l1_cap must be 0, 2048, 3072, 5120 or 7168");
   if (o.pool_entries < 0) return fail(SPGEMM_EINVAL, "pool_entries must be >= 0");
   if (o.long_path < 0 || o.long_path > 2) return fail(SPGEMM_EINVAL, "long_path must be 0, 1 or 2");
+  if (o.long_direct < 0 || o.long_direct > 1) return fail(SPGEMM_EINVAL, "long_direct must be 0 or 1");
   if (o.timing_mask < 0 || o.timing_mask >= (1 << SPGEMM_NSTAGES))
     return fail(SPGEMM_EINVAL, "timing_mask has bits beyond the stage count");
   return SPGEMM_OK;
@@ -433,8 +496,8 @@ extern "C" int spgemm_analyze(const spgemm_csr *A, const spgemm_csr *B,
   p->hsum = &p->hsum_store;
   p->hstat = &p->hstat_store;
   p->hpool = &p->hpool_store;
+  (void)hipGetDevice(&p->dev);
   if (o.timing) {
-    (void)hipGetDevice(&p->dev);
     p->tmask = o.timing_mask ? static_cast<uint32_t>(o.timing_mask)
                              : (1u << SPGEMM_NSTAGES) - 1u;
     for (auto &e : p->ev) {
@@ -546,6 +609,10 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   const bool want_win = p->opt.long_path == 2 || (p->opt.long_path == 0 && p->n <= kDenseCols);
   const bool use_win = nlong > 0 && p->opt.seg == 0 && want_win && S.w_none == 0;
   const bool legacy = nlong > 0 && !use_win;
+  // merge method with direct output: a counting pass sizes the pieces of
+  // split rows after phase 1, and phase 2 writes them straight into C
+  const bool direct =
+      legacy && p->opt.long_direct && S.n_split > 0 && long_direct_ok(p->lp, p->n);
   // C~ (hybrid sizes) plus the long-row tables in one allocation
   const int64_t nitems = legacy ? S.n_items : 0;
   const int64_t npieces = legacy ? S.n_pieces : 0;
@@ -572,8 +639,8 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   const size_t osp = L.add<int32_t>(legacy ? S.n_split : 0);
   const size_t opbc = L.add<int32_t>(legacy ? S.sum_u_multi : 0);
   const size_t opbv = L.add<T>(legacy ? S.sum_u_multi : 0);
-  const size_t oobc = L.add<int32_t>(legacy ? S.sum_u_multi : 0);
-  const size_t oobv = L.add<T>(legacy ? S.sum_u_multi : 0);
+  const size_t oobc = L.add<int32_t>(legacy && !direct ? S.sum_u_multi : 0);
+  const size_t oobv = L.add<T>(legacy && !direct ? S.sum_u_multi : 0);
   const size_t otmp = L.add<int64_t>(legacy ? long_table_tmp_len(nlong) : 0);
   // window method
   const size_t owr = L.add<WinRow>(use_win ? nlong : 0);
@@ -657,24 +724,28 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   ea.ct_val = ct_val;
   ea.rownnz = p->rownnz;
 
+  // the short-row kernels run on a second stream, beside the long-row work
+  // on the caller's stream: forked once C~ exists, joined before the row
+  // sizes are scanned
+  const hipStream_t es = fork_aux(p, s) ? p->aux : s;
   // ---- bin group 4: the four range bins, the largest first: its kernel
   // runs long enough for the host to queue the short ones behind it
-  stage_begin(p, SPGEMM_T_MEDIUM, s);
+  stage_begin(p, SPGEMM_T_MEDIUM, es);
   for (int b = 36; b >= 33; --b) {
     const int cap = static_cast<int>(next_pow2(p->be.e[b - 32]));
     const int64_t r0 = S.bin_off[b], r1 = S.bin_off[b + 1];
-    if (launch_esc<T>(ea, p->binlist + r0, r1 - r0, cap, p->n, s))
+    if (launch_esc<T>(ea, p->binlist + r0, r1 - r0, cap, p->n, es))
       return fail(SPGEMM_EINVAL, "no ESC kernel for this capacity");
   }
-  stage_end(p, SPGEMM_T_MEDIUM, s);
+  stage_end(p, SPGEMM_T_MEDIUM, es);
   // ---- stage 3, bin groups 2-3: one launch per power-of-two capacity
-  stage_begin(p, SPGEMM_T_TINY, s);
+  stage_begin(p, SPGEMM_T_TINY, es);
   if (p->opt.tiny_heap) {
     // bin 1 through the wavefront kernel, bins 2..edge[0] one kernel each
-    if (launch_esc<T>(ea, p->binlist + S.bin_off[1], S.bin_off[2] - S.bin_off[1], 1, p->n, s))
+    if (launch_esc<T>(ea, p->binlist + S.bin_off[1], S.bin_off[2] - S.bin_off[1], 1, p->n, es))
       return fail(SPGEMM_EINVAL, "no ESC kernel for this capacity");
     for (int b = 2; b <= p->be.e[0]; ++b)
-      if (launch_heap<T>(ea, p->binlist + S.bin_off[b], S.bin_off[b + 1] - S.bin_off[b], b, s))
+      if (launch_heap<T>(ea, p->binlist + S.bin_off[b], S.bin_off[b + 1] - S.bin_off[b], b, es))
         return fail(SPGEMM_EINVAL, "no heap kernel for this size");
   } else {
     int b = 1;
@@ -682,12 +753,12 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
       const int cap = static_cast<int>(next_pow2(b));
       const int hi = std::min<int>(cap, p->be.e[0]);
       const int64_t r0 = S.bin_off[b], r1 = S.bin_off[hi + 1];
-      if (launch_esc<T>(ea, p->binlist + r0, r1 - r0, cap, p->n, s))
+      if (launch_esc<T>(ea, p->binlist + r0, r1 - r0, cap, p->n, es))
         return fail(SPGEMM_EINVAL, "no ESC kernel for this capacity");
       b = hi + 1;
     }
   }
-  stage_end(p, SPGEMM_T_TINY, s);
+  stage_end(p, SPGEMM_T_TINY, es);
 
   // ---- bin group 5: long rows (merge method, split over work-groups)
   int64_t pool_entries = 0;
@@ -721,6 +792,11 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   la.list2 = list2;
   la.list3 = list3;
   la.ncols = p->n;
+  la.direct = direct ? 1 : 0;
+  la.c_col = nullptr;
+  la.c_val = nullptr;
+  la.rowoff = p->rowoff;
+  la.pscan = pscan;
   const bool spill_expected = S.spill_bound > 0 || p->opt.pool_entries > 0;
   auto new_pool = [&](int64_t entries, unsigned long long used) -> int {
     void *chunk = p->al.get(pool_chunk_bytes(entries, sizeof(T)), s);
@@ -800,8 +876,13 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
       la.work = nullptr;
       la.fail_list = fail_a;
     }
-    // phase 2: every output piece of the multi-segment rows
-    if (S.n_split > 0) {  // some row was split
+    // phase 2: every output piece of the multi-segment rows (with direct
+    // output: only their sizes now, the pieces after C is allocated)
+    if (direct) {
+      stage_begin(p, SPGEMM_T_LONG_SYM, s);
+      launch_piece_count<T>(la, npieces, s);
+      stage_end(p, SPGEMM_T_LONG_SYM, s);
+    } else if (S.n_split > 0) {  // some row was split
       stage_begin(p, SPGEMM_T_COMBINE, s);
       stage_begin(p, SPGEMM_T_COMBINE_WAVE, s);
       launch_combine_wave<T>(la, npieces, s);
@@ -815,6 +896,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   }
 
   // ---- stage 4a: row pointers of C (exclusive scan of the row sizes)
+  if (es != s) join_aux(p, s);
   stage_begin(p, SPGEMM_T_SCAN, s);
   scan_i64(p->rownnz, m, p->rowoff, p->part, s);
   stage_end(p, SPGEMM_T_SCAN, s);
@@ -849,7 +931,9 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
         la.fail_list = fl;
         launch_cstate_init(cstates, npieces, lcnt, s);
         la.fail_list2 = f2;
-        if (S.n_split > 0) {  // some row was split
+        if (direct) {
+          launch_piece_count<T>(la, npieces, s);
+        } else if (S.n_split > 0) {  // some row was split
           launch_combine_wave<T>(la, npieces, s);
           launch_combine_wave_large<T>(la, npieces, s);
           launch_combine_oneshot<T>(la, npieces, s);
@@ -880,6 +964,52 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   if (!cval) {
     p->al.put(ccol, s);
     return fail(SPGEMM_ENOMEM, "allocation of C failed");
+  }
+  if (direct) {
+    // phase 2 straight into C (pieces whose level-1 sequence spilled stay in
+    // the pool and are copied below); pool exhaustion relaunches the failed
+    // pieces until none is left
+    la.c_col = static_cast<int32_t *>(ccol);
+    la.c_val = static_cast<T *>(cval);
+    stage_begin(p, SPGEMM_T_COMBINE, s);
+    stage_begin(p, SPGEMM_T_COMBINE_WAVE, s);
+    launch_combine_wave<T>(la, npieces, s);
+    stage_end(p, SPGEMM_T_COMBINE_WAVE, s);
+    launch_combine_wave_large<T>(la, npieces, s);
+    launch_combine_oneshot<T>(la, npieces, s);
+    launch_combine<T>(la, npieces, s);
+    stage_end(p, SPGEMM_T_COMBINE, s);
+    if (spill_expected) {
+      unsigned int *f2 = fail2_a, *f2_other = fail2_b;
+      for (;;) {
+        if ((rc = read_status()) != SPGEMM_OK) {
+          p->al.put(ccol, s);
+          p->al.put(cval, s);
+          return rc;
+        }
+        const unsigned int nf2 = p->hstat->fail2;
+        if (nf2 == 0) break;
+        if (++I.realloc_rounds > 64) {
+          p->al.put(ccol, s);
+          p->al.put(cval, s);
+          return fail(SPGEMM_ENOMEM, "long-row pool keeps overflowing");
+        }
+        pool_entries *= 2;
+        if ((rc = new_pool(pool_entries, p->hstat->pool_used)) != SPGEMM_OK) {
+          p->al.put(ccol, s);
+          p->al.put(cval, s);
+          return rc;
+        }
+        la.work = reinterpret_cast<const int32_t *>(f2);
+        la.fail_list2 = f2_other;
+        launch_combine<T>(la, nf2, s);
+        std::swap(f2, f2_other);
+        la.work = nullptr;
+      }
+      I.pool_entries = pool_entries;
+      I.pool_used = static_cast<int64_t>(p->hstat->pool_used);
+      I.bytes_scratch = held_bytes(p);
+    }
   }
   if (use_win) {
     // numeric pass of the long rows, straight into C
@@ -948,6 +1078,7 @@ extern "C" int spgemm_compute(spgemm_plan plan, const spgemm_csr *A, const spgem
   p->stream = s;
   rc = p->dtype == SPGEMM_F64 ? compute_t<double>(p, A, B, C, s) : compute_t<float>(p, A, B, C, s);
   if (rc != SPGEMM_OK) {
+    join_aux(p, s);  // nothing on the second stream may outlive the scratch
     release_compute(p, s);
     return rc;
   }

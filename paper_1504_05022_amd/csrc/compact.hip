@@ -131,6 +131,7 @@ __global__ __launch_bounds__(CP_NT) void k_compact_pieces(CompactArgs<T> a, int6
   if (pc.cnt <= 0) return;
   const LongRow lr = a.lrows[pc.lrow];
   const int64_t dst = a.rowoff[lr.row] + a.pscan[pid] - a.pscan[lr.piece0];
+  if (pc.col == a.c_col + dst) return;  // written in place (direct output)
   const GLOBAL_AS int32_t *sc = as_global(pc.col);
   const GLOBAL_AS T *sv = as_global(reinterpret_cast<const T *>(pc.val));
   GLOBAL_AS int32_t *dc = as_global_mut(a.c_col + dst);

@@ -403,7 +403,25 @@ template <typename T> struct LongArgs {
   unsigned int *list2;    // pieces too large for the first wavefront pass
   unsigned int *list3;    // pieces too large for one wavefront
   int64_t ncols;
+  // direct output: the pieces of split rows go straight into C, at offsets
+  // from a counting pass run before C is allocated (else to ocol / oval)
+  int32_t direct;
+  int32_t *c_col;
+  T *c_val;
+  const int64_t *rowoff;  // row offsets of C
+  const int64_t *pscan;   // exclusive scan of the piece counts
 };
+
+// Whether every range of every split row is at most 2^kPieceCountLog
+// columns wide, so that the counting pass can count its columns in a
+// wavefront's LDS bitmap (the widest range belongs to the shortest split
+// row).
+constexpr int kPieceCountLog = 16;
+bool long_direct_ok(const LongParams &lp, int64_t ncols);
+// Distinct columns of every piece of a split row (one wavefront each,
+// from phase 1's sorted segments), into pieces[pid].cnt.
+template <typename T>
+void launch_piece_count(const LongArgs<T> &a, int64_t npieces, hipStream_t s);
 
 // Long-row table, work items and piece map (three launches).
 void launch_long_table(const int32_t *binlist, int64_t off, int64_t nlong, const int64_t *u,

@@ -47,6 +47,22 @@
 
 namespace spg {
 
+// Where piece pid of a split row writes its result: straight into C with
+// direct output, else at its place in the range buffer.
+template <typename T>
+DEVI void piece_out(const LongArgs<T> &a, int64_t pid, const LongRow &lr, int64_t obase,
+                    int32_t *&dcol, T *&dval) {
+  if (a.direct) {
+    const int64_t d = a.rowoff[lr.row] + a.pscan[pid] - a.pscan[lr.piece0];
+    dcol = a.c_col + d;
+    dval = a.c_val + d;
+  } else {
+    dcol = a.ocol + lr.pbase + obase;
+    dval = a.oval + lr.pbase + obase;
+  }
+}
+
+
 // Number of X elements among the first d outputs when merging sorted X and
 // Y with no common keys.
 DEVI int split_disjoint(const int32_t *xc, int nx, const int32_t *yc, int ny, int d) {
@@ -743,8 +759,7 @@ DEVI void combine_piece(LongArgs<T> &a, const int32_t pid) {
   if (!failed) {
     if (st.gcnt == 0) {
       // never spilled: L1 goes to the piece's own place (E entries)
-      dcol = a.ocol + lr.pbase + obase;
-      dval = a.oval + lr.pbase + obase;
+      piece_out(a, pid, lr, obase, dcol, dval);
       if (r > 0) copy_l1<T, NT>(l1c, l1v, r, dcol, dval);
       cnt = r;
     } else {
@@ -1286,8 +1301,9 @@ DEVI void combine1_body(LongArgs<T> &a, const int32_t pid, const int32_t lri, co
   int o = static_cast<int>(block_excl_sum<NT>(static_cast<int64_t>(nh), sh.scan, rtot));
   const int r = static_cast<int>(rtot);
   const LongRow lr = a.lrows[lri];
-  int32_t *dcol = a.ocol + lr.pbase + obase;
-  T *dval = a.oval + lr.pbase + obase;
+  int32_t *dcol;
+  T *dval;
+  piece_out(a, pid, lr, obase, dcol, dval);
 #pragma unroll
   for (int kk = 0; kk < KT; ++kk) {
     const int l = t * KT + kk;
@@ -1404,8 +1420,9 @@ DEVI void combine1_radix(LongArgs<T> &a, const int32_t pid, const int32_t lri, c
     r += sh.imax[x];
   }
   const LongRow lr = a.lrows[lri];
-  int32_t *dcol = a.ocol + lr.pbase + obase;
-  T *dval = a.oval + lr.pbase + obase;
+  int32_t *dcol;
+  T *dval;
+  piece_out(a, pid, lr, obase, dcol, dval);
   const int32_t cb = c0 + cmin;
 #pragma unroll
   for (int kk = 0; kk < KT; ++kk) {
@@ -1956,8 +1973,9 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
   int32_t *sc = reinterpret_cast<int32_t *>(lds_a);
   T *sv = lds_b;
   const int r = fold_runs<T, WAVE, K, Key>(key, tn, pv, sc, sv, c0);
-  int32_t *dcol = a.ocol + lr.pbase + obase;
-  T *dval = a.oval + lr.pbase + obase;
+  int32_t *dcol;
+  T *dval;
+  piece_out(a, pid, lr, obase, dcol, dval);
   for (int x = pos; x < r; x += WAVE) {
     dcol[x] = sc[x];
     dval[x] = sv[x];
@@ -2393,5 +2411,135 @@ template void launch_combine_wave<float>(const LongArgs<float> &, int64_t, hipSt
 template void launch_combine_wave<double>(const LongArgs<double> &, int64_t, hipStream_t);
 template void launch_combine_wave_large<float>(const LongArgs<float> &, int64_t, hipStream_t);
 template void launch_combine_wave_large<double>(const LongArgs<double> &, int64_t, hipStream_t);
+
+
+// ------------------------------------------------------- counting pass
+//
+// Distinct columns of each piece (column range) of a split row, from the
+// sorted segments phase 1 wrote: every entry of the range in every segment
+// sets its bit in a wavefront's LDS bitmap of the range's 2^shift columns
+// (at most 2^kPieceCountLog, checked on the host), and the bits are
+// counted.  A segment's part of the range is one run of its sorted
+// partial.  Pieces of one-segment rows keep the count phase 1 wrote.
+constexpr int PC_KS = 8;  // segments per lane (PC_KS * 64 >= the most segments of a row)
+
+template <typename T>
+__global__ __launch_bounds__(WAVE) void k_piece_count(LongArgs<T> a, int64_t npieces) {
+  constexpr int NWORDS = (1 << kPieceCountLog) / 32;
+  constexpr int MAXSEG = PC_KS * WAVE;
+  __shared__ uint32_t bm[NWORDS];
+  __shared__ int32_t pre[MAXSEG];  // start of each segment's part in the range's stream
+  __shared__ int32_t src[MAXSEG];  // its first entry in the row's partials
+  const int ln = lane();
+  const int64_t pid = xcd_block_id<16>();
+  if (pid >= npieces) return;
+  const int32_t lri = a.piece_lrow[pid];
+  const LongRow lr = a.lrows[lri];
+  if (lr.nseg <= 1 || lr.shift > kPieceCountLog || lr.nseg > MAXSEG) return;  // (host rules out)
+  const int32_t b = static_cast<int32_t>(pid - lr.piece0);
+  const int64_t c0 = static_cast<int64_t>(b) << lr.shift;
+  const int64_t width64 = (int64_t(1) << lr.shift) < (a.ncols - c0) ? (int64_t(1) << lr.shift)
+                                                                   : (a.ncols - c0);
+  const int nwords = static_cast<int>((width64 + 31) >> 5);
+  for (int q = ln; q < nwords; q += WAVE) bm[q] = 0u;
+  const int32_t nseg = lr.nseg;
+  const GLOBAL_AS int32_t *lo_row = as_global(a.split + lr.sbase + static_cast<int64_t>(b) * nseg);
+  const GLOBAL_AS int32_t *hi_row = as_global(a.split + lr.sbase + static_cast<int64_t>(b + 1) * nseg);
+  const GLOBAL_AS int32_t *pcol = as_global(a.pcol + lr.pbase);
+  // every segment's bounds in one round trip (lane p: segments p*KS ..),
+  // then the parts laid end to end by one scan
+  int32_t slo[PC_KS], slen[PC_KS];
+#pragma unroll
+  for (int j = 0; j < PC_KS; ++j) {
+    const int32_t sg = ln * PC_KS + j;
+    const int32_t sc = sg < nseg ? sg : nseg - 1;
+    slo[j] = lo_row[sc];
+    slen[j] = hi_row[sc];
+  }
+  int32_t tot_len = 0;
+#pragma unroll
+  for (int j = 0; j < PC_KS; ++j) {
+    const bool in = ln * PC_KS + j < nseg;
+    const int32_t lo = in ? max(slo[j], 0) : 0;
+    slen[j] = in ? max(slen[j] - lo, 0) : 0;
+    slo[j] = lo;
+    tot_len += slen[j];
+  }
+  const int32_t incl = group_incl_sum<WAVE>(tot_len);
+  const int32_t E = __shfl(incl, WAVE - 1, WAVE);
+  {
+    int32_t run = incl - tot_len;
+#pragma unroll
+    for (int j = 0; j < PC_KS; ++j) {
+      const int32_t sg = ln * PC_KS + j;
+      if (sg < nseg) {
+        pre[sg] = run;
+        src[sg] = static_cast<int32_t>(static_cast<int64_t>(sg) * lr.segp + slo[j]);
+      }
+      run += slen[j];
+    }
+  }
+  wave_sync();
+  // lanes on consecutive entries of the stream, four at a time; the entry's
+  // part is the last one starting at or before it
+  for (int32_t x0 = 0; x0 < E; x0 += 4 * WAVE) {
+    int32_t c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t x = x0 + u * WAVE + ln;
+      const int32_t xc = x < E ? x : E - 1;
+      int lo = 0, hi = nseg - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= xc)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      c[u] = pcol[src[lo] + (xc - pre[lo])];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (x0 + u * WAVE + ln < E) {
+        const uint32_t x = static_cast<uint32_t>(c[u] - c0);
+        atomicOr(&bm[x >> 5], 1u << (x & 31));
+      }
+    }
+  }
+  wave_sync();
+  int64_t cnt = 0;
+  for (int q = ln; q < nwords; q += WAVE) cnt += __popc(bm[q]);
+  cnt = __shfl(static_cast<long long>(group_incl_sum<WAVE>(cnt)), WAVE - 1, WAVE);
+  if (ln == 0) {
+    Piece pc;
+    pc.col = nullptr;
+    pc.val = nullptr;
+    pc.cnt = cnt;
+    pc.lrow = lri;
+    pc.pad = 0;
+    a.pieces[pid] = pc;
+  }
+}
+
+template <typename T>
+void launch_piece_count(const LongArgs<T> &a, int64_t npieces, hipStream_t s) {
+  if (npieces <= 0) return;
+  hipLaunchKernelGGL((k_piece_count<T>), dim3(npieces), dim3(WAVE), 0, s, a, npieces);
+}
+
+bool long_direct_ok(const LongParams &lp, int64_t ncols) {
+  if (lp.segp < 0) return false;
+  // rows are split only above max(segp, single) products; the range width
+  // shrinks as u grows
+  const int64_t umin = std::max<int64_t>(lp.segp, lp.single) + 1;
+  const int64_t w = (ncols * lp.cb + umin - 1) / umin;
+  int32_t shift = ceil_log2_i64(w > 1 ? w : 1);
+  if (shift < lp.minw_shift) shift = lp.minw_shift;
+  if (shift > lp.maxw_shift) shift = lp.maxw_shift;
+  return shift <= kPieceCountLog && lp.maxs <= PC_KS * WAVE;
+}
+
+template void launch_piece_count<float>(const LongArgs<float> &, int64_t, hipStream_t);
+template void launch_piece_count<double>(const LongArgs<double> &, int64_t, hipStream_t);
 
 }  // namespace spg

@@ -48,7 +48,7 @@ class Options(ctypes.Structure):
                 ("pool_entries", ctypes.c_int64), ("validate", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("timing_mask", ctypes.c_int32),
                 ("tiny_heap", ctypes.c_int32), ("long_path", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("long_direct", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

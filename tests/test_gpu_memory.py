@@ -38,7 +38,7 @@ def _alloc_size(b):
     return b if b else 256
 
 
-@pytest.mark.parametrize("case", ["workload1", "merge", "windows", "dense", "pool_growth"])
+@pytest.mark.parametrize("case", ["workload1", "merge", "direct", "windows", "dense", "pool_growth"])
 def test_bytes_scratch_is_the_plans_peak(case):
     import torch
     from paper_1504_05022_amd import lib as L
@@ -46,10 +46,10 @@ def test_bytes_scratch_is_the_plans_peak(case):
     if case == "workload1":
         A, _ = S.config1()
         B = A
-    elif case in ("merge", "windows"):
+    elif case in ("merge", "direct", "windows"):
         A, _ = S.config2(n=20000, cap=3000)
         B = A
-        opts = {"long_path": 2 if case == "windows" else 1}
+        opts = {"long_path": 2 if case == "windows" else 1, "long_direct": int(case == "direct")}
     elif case == "dense":
         A, B = S.crafted_rows([600, 3000, 40000, 513, 20], n=3000, dtype=np.float32)
     else:

@@ -459,3 +459,23 @@ def test_window_method_matches_segment_method():
     (rp1, ci1, v1), i1 = check(A, A, long_path=1)
     assert np.array_equal(rp0, rp1) and np.array_equal(ci0, ci1)
     assert np.array_equal(v0, v1)
+
+
+@pytest.mark.parametrize("case", ["workload2", "crowded", "duplicates"])
+def test_direct_output_matches_copy(case):
+    """Merge method with long_direct = 1: the pieces of split rows are sized
+    by a counting pass over phase 1's sorted segments and written straight
+    into C (no range buffer); C equals the default's bit for bit, on less
+    device memory.  Crowded and duplicate-heavy columns send ranges through
+    the larger-tile and level-1 kernels too."""
+    if case == "workload2":
+        A, _ = S.config2(n=30000, cap=5000)
+        B = A
+    elif case == "crowded":
+        A, B = S.crafted_rows([1500, 3000, 9000, 30000, 2049], n=60000, col_range=3000)
+    else:
+        A, B = S.crafted_rows([3000, 5000, 1200], n=60000, col_range=40)
+    (rp0, ci0, v0), i0 = check(A, B, exact=False, long_path=1)
+    (rp1, ci1, v1), i1 = check(A, B, exact=False, long_path=1, long_direct=1)
+    assert np.array_equal(rp0, rp1) and np.array_equal(ci0, ci1) and np.array_equal(v0, v1)
+    assert i1.bytes_scratch < i0.bytes_scratch
