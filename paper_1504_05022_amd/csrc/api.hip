@@ -725,40 +725,48 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   ea.rownnz = p->rownnz;
 
   // the short-row kernels run on a second stream, beside the long-row work
-  // on the caller's stream: forked once C~ exists, joined before the row
-  // sizes are scanned
+  // on the caller's stream: forked here, once C~ exists (the second stream
+  // waits for what the caller's stream holds now, not for the long-row
+  // kernels queued next), queued after the first long-row kernels so that
+  // the host gets those going first, joined before the row sizes are scanned
   const hipStream_t es = fork_aux(p, s) ? p->aux : s;
-  // ---- bin group 4: the four range bins, the largest first: its kernel
-  // runs long enough for the host to queue the short ones behind it
-  stage_begin(p, SPGEMM_T_MEDIUM, es);
-  for (int b = 36; b >= 33; --b) {
-    const int cap = static_cast<int>(next_pow2(p->be.e[b - 32]));
-    const int64_t r0 = S.bin_off[b], r1 = S.bin_off[b + 1];
-    if (launch_esc<T>(ea, p->binlist + r0, r1 - r0, cap, p->n, es))
-      return fail(SPGEMM_EINVAL, "no ESC kernel for this capacity");
-  }
-  stage_end(p, SPGEMM_T_MEDIUM, es);
-  // ---- stage 3, bin groups 2-3: one launch per power-of-two capacity
-  stage_begin(p, SPGEMM_T_TINY, es);
-  if (p->opt.tiny_heap) {
-    // bin 1 through the wavefront kernel, bins 2..edge[0] one kernel each
-    if (launch_esc<T>(ea, p->binlist + S.bin_off[1], S.bin_off[2] - S.bin_off[1], 1, p->n, es))
-      return fail(SPGEMM_EINVAL, "no ESC kernel for this capacity");
-    for (int b = 2; b <= p->be.e[0]; ++b)
-      if (launch_heap<T>(ea, p->binlist + S.bin_off[b], S.bin_off[b + 1] - S.bin_off[b], b, es))
-        return fail(SPGEMM_EINVAL, "no heap kernel for this size");
-  } else {
-    int b = 1;
-    while (b <= p->be.e[0]) {
-      const int cap = static_cast<int>(next_pow2(b));
-      const int hi = std::min<int>(cap, p->be.e[0]);
-      const int64_t r0 = S.bin_off[b], r1 = S.bin_off[hi + 1];
+  bool short_done = false;
+  auto launch_short_rows = [&]() -> int {
+    if (short_done) return SPGEMM_OK;
+    short_done = true;
+    // ---- bin group 4: the four range bins, the largest first: its kernel
+    // runs long enough for the host to queue the short ones behind it
+    stage_begin(p, SPGEMM_T_MEDIUM, es);
+    for (int b = 36; b >= 33; --b) {
+      const int cap = static_cast<int>(next_pow2(p->be.e[b - 32]));
+      const int64_t r0 = S.bin_off[b], r1 = S.bin_off[b + 1];
       if (launch_esc<T>(ea, p->binlist + r0, r1 - r0, cap, p->n, es))
         return fail(SPGEMM_EINVAL, "no ESC kernel for this capacity");
-      b = hi + 1;
     }
-  }
-  stage_end(p, SPGEMM_T_TINY, es);
+    stage_end(p, SPGEMM_T_MEDIUM, es);
+    // ---- stage 3, bin groups 2-3: one launch per power-of-two capacity
+    stage_begin(p, SPGEMM_T_TINY, es);
+    if (p->opt.tiny_heap) {
+      // bin 1 through the wavefront kernel, bins 2..edge[0] one kernel each
+      if (launch_esc<T>(ea, p->binlist + S.bin_off[1], S.bin_off[2] - S.bin_off[1], 1, p->n, es))
+        return fail(SPGEMM_EINVAL, "no ESC kernel for this capacity");
+      for (int b = 2; b <= p->be.e[0]; ++b)
+        if (launch_heap<T>(ea, p->binlist + S.bin_off[b], S.bin_off[b + 1] - S.bin_off[b], b, es))
+          return fail(SPGEMM_EINVAL, "no heap kernel for this size");
+    } else {
+      int b = 1;
+      while (b <= p->be.e[0]) {
+        const int cap = static_cast<int>(next_pow2(b));
+        const int hi = std::min<int>(cap, p->be.e[0]);
+        const int64_t r0 = S.bin_off[b], r1 = S.bin_off[hi + 1];
+        if (launch_esc<T>(ea, p->binlist + r0, r1 - r0, cap, p->n, es))
+          return fail(SPGEMM_EINVAL, "no ESC kernel for this capacity");
+        b = hi + 1;
+      }
+    }
+    stage_end(p, SPGEMM_T_TINY, es);
+    return SPGEMM_OK;
+  };
 
   // ---- bin group 5: long rows (merge method, split over work-groups)
   int64_t pool_entries = 0;
@@ -826,6 +834,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     win_plan_launch(p->binlist + S.bin_off[LONG_BIN], nlong, p->u, p->n, static_cast<int>(sizeof(T)),
                     wbsum, wrows, witems, w_items, wsegs, w_segs, wslot, w_slots, A->row_ptr, p->P,
                     s);
+    if ((rc = launch_short_rows()) != SPGEMM_OK) return rc;
     stage_begin(p, SPGEMM_T_LONG_WAVE, s);
     win_partition<T>(ea, wrows, wsegs, w_segs, wtable, wpkey, wpval, s);
     stage_end(p, SPGEMM_T_LONG_WAVE, s);
@@ -850,6 +859,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
     stage_begin(p, SPGEMM_T_LONG_WAVE, s);
     launch_long_wave<T>(la, nitems, s);
     stage_end(p, SPGEMM_T_LONG_WAVE, s);
+    if ((rc = launch_short_rows()) != SPGEMM_OK) return rc;
     launch_long_wave_large<T>(la, nitems, s);
     launch_long_oneshot<T>(la, nitems, s);
     if (launch_long<T>(la, nitems, p->l1cap, s))
@@ -896,6 +906,7 @@ int compute_t(spgemm_plan p, const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
   }
 
   // ---- stage 4a: row pointers of C (exclusive scan of the row sizes)
+  if ((rc = launch_short_rows()) != SPGEMM_OK) return rc;  // no long rows
   if (es != s) join_aux(p, s);
   stage_begin(p, SPGEMM_T_SCAN, s);
   scan_i64(p->rownnz, m, p->rowoff, p->part, s);
