@@ -134,6 +134,9 @@ typedef struct {
                            counting pass sizes them first and they are
                            written straight into C (no range buffer: less
                            device memory, about 5% slower on workload 2)   */
+  int32_t batch_shapes; /* batched form: 0 = the autotuner picks the tile-shape
+                           set (default); 1..3 = shape set 0..2 fixed         */
+  int32_t pad_;
 } spgemm_options;
 
 #define SPGEMM_NBINS 38
@@ -271,20 +274,23 @@ int spgemm_multiply(const spgemm_csr *A, const spgemm_csr *B, const spgemm_optio
 /* ------------------------------------------------------------------------
  * Batched products (extension beyond the paper): many independent
  * C_p = A_p * B_p of uneven sizes and mixed binary32/binary64 values,
- * computed by one persistent kernel launch replayed from a HIP graph.
+ * computed by one HIP graph of one kernel launch per capacity class.
  */
 typedef struct spgemm_batch_s *spgemm_batch;
 
 typedef struct {
   int32_t count;        /* problems                                           */
   int32_t fallback;     /* problems recomputed with the plain path per run    */
-  int32_t grid;         /* work-groups of the persistent kernel               */
-  int32_t pad;
-  int64_t items;        /* work items in the queue                            */
+  int32_t grid;         /* kernel launches in the graph (nonempty classes)    */
+  int32_t shapes;       /* tile-shape set chosen by the autotuner: 0 = the
+                           plain path's (G lanes, K products per lane) per
+                           capacity, 1 = wider groups, 2 = narrower groups   */
+  int64_t items;        /* work items (one work-group each)                   */
   int64_t flops;        /* sum of 2 * sum(u_i) over the problems              */
   int64_t nnz_c;        /* sum of nnz(C_p)                                    */
   int32_t bin_edges[5]; /* thresholds chosen by the autotuner                 */
-  float tune_ms[4];     /* timed candidates (ms per run)                      */
+  float tune_ms[12];    /* timed candidates (ms per run): threshold set t and
+                           shape set k at [3 t + k]; 0 where not timed       */
 } spgemm_batch_stats;
 
 /*

@@ -385,6 +385,8 @@ int check_options(const spgemm_options &o) {
   if (o.pool_entries < 0) return fail(SPGEMM_EINVAL, "pool_entries must be >= 0");
   if (o.long_path < 0 || o.long_path > 2) return fail(SPGEMM_EINVAL, "long_path must be 0, 1 or 2");
   if (o.long_direct < 0 || o.long_direct > 1) return fail(SPGEMM_EINVAL, "long_direct must be 0 or 1");
+  if (o.batch_shapes < 0 || o.batch_shapes > 3)
+    return fail(SPGEMM_EINVAL, "batch_shapes must be 0 (autotune) or 1..3");
   if (o.timing_mask < 0 || o.timing_mask >= (1 << SPGEMM_NSTAGES))
     return fail(SPGEMM_EINVAL, "timing_mask has bits beyond the stage count");
   return SPGEMM_OK;

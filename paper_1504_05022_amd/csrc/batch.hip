@@ -1,17 +1,18 @@
 // Batched SpGEMM: many independent products C_p = A_p * B_p of uneven sizes
-// and mixed precision in one persistent kernel launch, replayed from a HIP
-// graph.
+// and mixed precision in one HIP graph of at most eleven kernel launches.
 //
 // batch_create analyzes every problem (stages 1-2, Algorithms 2 and 3),
 // computes every C_p once with the plain path to fix its structure and
-// row pointers, then builds one work queue over all problems: every item is
+// row pointers, then builds one item list over all problems: every item is
 // a group of rows of one problem from one bin (capacity class of the
-// wavefront expand-sort-compress).  An autotuner times the queue under a few
-// bin-threshold sets and keeps the fastest; the winning queue is captured in
-// a graph (a queue reset kernel plus the persistent kernel).  batch_run
-// replays the graph: work-groups take items from an atomic queue head until
-// it passes the end (every work-group reaches that exit), and every row is
-// recomputed straight into its place in C_p, whose row offsets are known.
+// wavefront expand-sort-compress).  Items are grouped by class, and each
+// class is one launch with one work-group per item, so every kernel holds
+// only its own tile's registers and LDS.  An autotuner times the launches
+// under a few bin-threshold sets and, for each, three tile-shape sets (lanes
+// per row against products per lane of every capacity class) and keeps the
+// fastest pair; its launches are captured in a graph.  batch_run replays the
+// graph: every row is recomputed straight into its place in C_p, whose row
+// offsets are known.
 //
 // Scope: every row of every problem must have at most 1024 products and
 // 32-bit sort keys (n_p * 1024 < 2^32); other problems are recomputed with
@@ -19,7 +20,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstring>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -72,50 +75,59 @@ DEVI EscArgs<T> esc_args_of(const BatchProblem &bp) {
   return e;
 }
 
-template <typename T>
-DEVI void batch_item(const BatchItem &it, const BatchProblem &bp, unsigned char *lds) {
-  const EscArgs<T> ea = esc_args_of<T>(bp);
+// Tile shape (G lanes per row, K products per lane, G * K = capacity) of
+// every capacity class in each of the shape sets the autotuner tries: the
+// plain path's shapes, wider groups (more lanes, fewer products per lane:
+// shorter sorts, more rows' latency in flight per lane) and narrower ones
+// (up to 8 products per lane below the two largest classes: more rows per
+// work-group).
+constexpr int kBatchShapeSets = 3;
+__host__ __device__ constexpr int batch_class_g(int set, int c) {
+  constexpr int G[kBatchShapeSets][kBatchNumClasses] = {
+      {1, 2, 4, 4, 4, 8, 16, 16, 32, 64, 64},
+      {1, 2, 4, 8, 16, 16, 32, 32, 64, 64, 64},
+      {1, 1, 1, 1, 2, 4, 8, 16, 32, 32, 64}};
+  return G[set][c];
+}
+
+// One work-group per item of capacity class C under shape set SET: the rows
+// of one problem's bin list, expanded, sorted and compressed straight into
+// their places in C_p (binary32 and binary64 problems alike).  One launch
+// per class over the items of every problem: each kernel is held only to
+// its own tile's registers and LDS (a single kernel over all classes would
+// be held to the largest tile's).
+template <int SET, int C>
+__global__ __launch_bounds__(ESC_NT) void k_batch_class(const BatchItem *items,
+                                                        const BatchProblem *probs) {
+  constexpr int G = batch_class_g(SET, C);
+  constexpr int K = batch_class_cap(C) / G;
+  __shared__ __align__(16) unsigned char lds[EscShape<double, G, K, uint32_t>::lds_bytes];
+  const BatchItem it = items[blockIdx.x];
+  const BatchProblem bp = probs[it.prob];
   const int32_t *rows = bp.binlist + it.start;
-  const int64_t n = it.count;
-  switch (it.cls) {
-    case 0: esc_rows<T, 1, 1, uint32_t>(ea, rows, 0, n, lds); break;
-    case 1: esc_rows<T, 2, 1, uint32_t>(ea, rows, 0, n, lds); break;
-    case 2: esc_rows<T, 4, 1, uint32_t>(ea, rows, 0, n, lds); break;
-    case 3: esc_rows<T, 4, 2, uint32_t>(ea, rows, 0, n, lds); break;
-    case 4: esc_rows<T, 4, 4, uint32_t>(ea, rows, 0, n, lds); break;
-    case 5: esc_rows<T, 8, 4, uint32_t>(ea, rows, 0, n, lds); break;
-    case 6: esc_rows<T, 16, 4, uint32_t>(ea, rows, 0, n, lds); break;
-    case 7: esc_rows<T, 16, 8, uint32_t>(ea, rows, 0, n, lds); break;
-    case 8: esc_rows<T, 32, 8, uint32_t>(ea, rows, 0, n, lds); break;
-    case 9: esc_rows<T, 64, 8, uint32_t>(ea, rows, 0, n, lds); break;
-    case 10: esc_rows<T, 64, 16, uint32_t>(ea, rows, 0, n, lds); break;
-    default: break;
-  }
+  if (bp.dtype == SPGEMM_F64)
+    esc_rows<double, G, K, uint32_t>(esc_args_of<double>(bp), rows, 0, it.count, lds);
+  else
+    esc_rows<float, G, K, uint32_t>(esc_args_of<float>(bp), rows, 0, it.count, lds);
 }
 
-constexpr size_t kBatchLds = EscShape<double, 64, 16, uint32_t>::lds_bytes;
+using BatchKernel = void (*)(const BatchItem *, const BatchProblem *);
 
-__global__ __launch_bounds__(ESC_NT) void k_batch(const BatchItem *items, int64_t nitems,
-                                                  const BatchProblem *probs,
-                                                  unsigned long long *head) {
-  __shared__ __align__(16) unsigned char lds[kBatchLds];
-  __shared__ unsigned long long cur;
-  for (;;) {
-    if (threadIdx.x == 0) cur = atomicAdd(head, 1ull);
-    __syncthreads();
-    const unsigned long long w = cur;
-    __syncthreads();
-    if (w >= static_cast<unsigned long long>(nitems)) break;
-    const BatchItem it = items[w];
-    const BatchProblem bp = probs[it.prob];
-    if (bp.dtype == SPGEMM_F64)
-      batch_item<double>(it, bp, lds);
-    else
-      batch_item<float>(it, bp, lds);
-  }
+template <int SET, int... C>
+constexpr std::array<BatchKernel, sizeof...(C)> batch_kernels_of(std::integer_sequence<int, C...>) {
+  return {{&k_batch_class<SET, C>...}};
 }
 
-__global__ void k_batch_reset(unsigned long long *head) { *head = 0ull; }
+// kernel of (shape set, class)
+BatchKernel batch_kernel(int set, int c) {
+  static const std::array<BatchKernel, kBatchNumClasses> k0 =
+      batch_kernels_of<0>(std::make_integer_sequence<int, kBatchNumClasses>{});
+  static const std::array<BatchKernel, kBatchNumClasses> k1 =
+      batch_kernels_of<1>(std::make_integer_sequence<int, kBatchNumClasses>{});
+  static const std::array<BatchKernel, kBatchNumClasses> k2 =
+      batch_kernels_of<2>(std::make_integer_sequence<int, kBatchNumClasses>{});
+  return set == 1 ? k1[c] : (set == 2 ? k2[c] : k0[c]);
+}
 
 }  // namespace spg
 
@@ -133,8 +145,8 @@ int bfail(int code, const std::string &msg) {
 struct Candidate {
   int32_t edges[5];
   std::vector<spgemm_plan> plans;
-  std::vector<BatchItem> items;
-  float ms = 0.f;
+  std::vector<BatchItem> items[kBatchShapeSets];  // per tile-shape set
+  float ms[kBatchShapeSets] = {};
 };
 
 }  // namespace
@@ -151,10 +163,11 @@ struct spgemm_batch_s {
   std::vector<spgemm_plan> plans;  // winning candidate's plans (bin lists, P, u)
   std::vector<int32_t> fallback;   // problems recomputed with the plain path
   std::vector<int64_t *> rowoff;   // per problem, copied from the first compute
-  void *dmem = nullptr;            // problems table + items + queue head
+  void *dmem = nullptr;            // problems table + items
   void *doff = nullptr;            // row offsets of all problems
   int64_t nitems = 0;
-  int grid = 0;
+  int shape_set = 0;  // tile shapes chosen by the autotuner
+  int64_t cls_off[kBatchNumClasses + 1] = {};  // items of class c: [cls_off[c], cls_off[c+1])
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   spgemm_batch_stats stats{};
@@ -189,13 +202,11 @@ int class_of_cap(int64_t cap) {
 }
 
 // rows per work-group pass of each class (256 / G)
-int class_rpb(int c) {
-  static const int G[kBatchNumClasses] = {1, 2, 4, 4, 4, 8, 16, 16, 32, 64, 64};
-  return ESC_NT / G[c];
-}
+int class_rpb(int set, int c) { return ESC_NT / batch_class_g(set, c); }
 
-// Work items of one analyzed problem (bins 1..36) under its thresholds.
-void build_items(int32_t prob, const spgemm_info &I, const int32_t edges[5],
+// Work items of one analyzed problem (bins 1..36) under its thresholds and
+// a tile-shape set.
+void build_items(int32_t prob, const spgemm_info &I, const int32_t edges[5], int set,
                  std::vector<BatchItem> &out) {
   // bin segment starts from the per-bin counts (bins are stored in order)
   int64_t off[SPGEMM_NBINS + 1];
@@ -203,7 +214,7 @@ void build_items(int32_t prob, const spgemm_info &I, const int32_t edges[5],
   for (int b = 0; b < SPGEMM_NBINS; ++b) off[b + 1] = off[b] + I.bin_count[b];
   auto emit = [&](int b_lo, int b_hi, int64_t cap) {
     const int c = class_of_cap(cap);
-    const int rpb = class_rpb(c);
+    const int rpb = class_rpb(set, c);
     for (int64_t r = off[b_lo]; r < off[b_hi + 1]; r += rpb) {
       BatchItem it;
       it.prob = prob;
@@ -270,9 +281,16 @@ int spgemm_batch_create(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
                                       {16, 64, 256, 512, 1024},
                                       {32, 128, 256, 512, 1024},
                                       {8, 32, 128, 512, 1024}};
-  // the autotuner runs unless the caller fixed the thresholds
+  // the autotuner runs unless the caller fixed the thresholds; a fixed
+  // tile-shape set is timed alone
+  if (b->opt.batch_shapes < 0 || b->opt.batch_shapes > kBatchShapeSets) {
+    spgemm_batch_destroy(b);
+    return bfail(SPGEMM_EINVAL, "batch_shapes must be 0 (autotune) or 1..3");
+  }
   const bool tune = std::memcmp(b->opt.bin_edges, kDefaultEdges, sizeof(kDefaultEdges)) == 0;
   const int ncand = tune ? 4 : 1;
+  const int set_lo = b->opt.batch_shapes ? b->opt.batch_shapes - 1 : 0;
+  const int set_hi = b->opt.batch_shapes ? b->opt.batch_shapes : kBatchShapeSets;
   std::vector<Candidate> cands(ncand);
   std::vector<char> batched(count, 1);
   std::vector<int64_t> m_of(count, 0);
@@ -318,11 +336,13 @@ int spgemm_batch_create(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
                                       hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) rc = bfail(SPGEMM_EHIP, "row offset copy failed");
       }
-      if (batched[p]) build_items(p, I, cd.edges, cd.items);
+      if (batched[p])
+        for (int set = 0; set < kBatchShapeSets; ++set) build_items(p, I, cd.edges, set, cd.items[set]);
     }
-    // largest rows first, so the queue ends with short items
-    std::stable_sort(cd.items.begin(), cd.items.end(),
-                     [](const BatchItem &x, const BatchItem &y) { return x.cls > y.cls; });
+    // items grouped by class (one launch each)
+    for (auto &v : cd.items)
+      std::stable_sort(v.begin(), v.end(),
+                       [](const BatchItem &x, const BatchItem &y) { return x.cls < y.cls; });
   }
   if (rc != SPGEMM_OK) {
     for (auto &cd : cands) destroy_plans(cd.plans);
@@ -332,13 +352,13 @@ int spgemm_batch_create(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
   for (int32_t p = 0; p < count; ++p)
     if (!batched[p]) b->fallback.push_back(p);
 
-  // device tables: problems, the largest item list, queue head
+  // device tables: problems and the largest item list
   size_t maxitems = 1;
-  for (auto &cd : cands) maxitems = std::max(maxitems, cd.items.size());
+  for (auto &cd : cands)
+    for (auto &v : cd.items) maxitems = std::max(maxitems, v.size());
   const size_t oprob = 0;
   const size_t oitems = (sizeof(BatchProblem) * std::max(count, 1) + 255) & ~size_t(255);
-  const size_t ohead = (oitems + sizeof(BatchItem) * maxitems + 255) & ~size_t(255);
-  b->dmem = b->get(ohead + 256, s);
+  b->dmem = b->get(oitems + sizeof(BatchItem) * maxitems, s);
   if (!b->dmem) {
     for (auto &cd : cands) destroy_plans(cd.plans);
     spgemm_batch_destroy(b);
@@ -346,18 +366,16 @@ int spgemm_batch_create(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
   }
   BatchProblem *dprob = reinterpret_cast<BatchProblem *>(static_cast<char *>(b->dmem) + oprob);
   BatchItem *ditems = reinterpret_cast<BatchItem *>(static_cast<char *>(b->dmem) + oitems);
-  unsigned long long *dhead =
-      reinterpret_cast<unsigned long long *>(static_cast<char *>(b->dmem) + ohead);
 
-  int occ = 0;
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(k_batch),
-                                                     ESC_NT, 0);
-  int dev = 0, ncu = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  b->grid = std::max(1, occ) * ncu;
-
-  auto upload = [&](Candidate &cd) -> int {
+  // item ranges of every class in a list sorted by ascending class
+  auto class_ranges = [](const std::vector<BatchItem> &v, int64_t (&off)[kBatchNumClasses + 1]) {
+    int64_t k = 0;
+    for (int c = 0; c <= kBatchNumClasses; ++c) {
+      while (k < static_cast<int64_t>(v.size()) && v[k].cls < c) ++k;
+      off[c] = k;
+    }
+  };
+  auto upload = [&](Candidate &cd, int set) -> int {
     std::vector<BatchProblem> hp(count);
     for (int32_t p = 0; p < count; ++p) {
       BatchProblem &q = hp[p];
@@ -381,41 +399,54 @@ int spgemm_batch_create(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
         hipMemcpyAsync(dprob, hp.data(), sizeof(BatchProblem) * count, hipMemcpyHostToDevice,
                        s) != hipSuccess)
       return bfail(SPGEMM_EHIP, "problem table upload failed");
-    if (!cd.items.empty() &&
-        hipMemcpyAsync(ditems, cd.items.data(), sizeof(BatchItem) * cd.items.size(),
+    if (!cd.items[set].empty() &&
+        hipMemcpyAsync(ditems, cd.items[set].data(), sizeof(BatchItem) * cd.items[set].size(),
                        hipMemcpyHostToDevice, s) != hipSuccess)
-      return bfail(SPGEMM_EHIP, "work queue upload failed");
+      return bfail(SPGEMM_EHIP, "item list upload failed");
     if (hipStreamSynchronize(s) != hipSuccess) return bfail(SPGEMM_EHIP, "upload sync failed");
     return SPGEMM_OK;
   };
-  auto launch = [&](int64_t nitems) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, dhead);
-    if (nitems > 0)
-      hipLaunchKernelGGL(k_batch, dim3(b->grid), dim3(ESC_NT), 0, s, ditems, nitems, dprob, dhead);
+  // one launch per class, the largest rows first (their work-groups run
+  // longest), one work-group per item
+  auto enqueue = [&](hipStream_t st, const int64_t (&off)[kBatchNumClasses + 1], int set) {
+    for (int c = kBatchNumClasses - 1; c >= 0; --c) {
+      const int64_t n = off[c + 1] - off[c];
+      if (n > 0)
+        hipLaunchKernelGGL(batch_kernel(set, c), dim3(static_cast<unsigned int>(n)), dim3(ESC_NT),
+                           0, st, ditems + off[c], static_cast<const BatchProblem *>(dprob));
+    }
   };
 
-  // autotuner: time the persistent kernel under every candidate
-  int best = 0;
-  if (ncand > 1) {
+  // autotuner: time the class launches under every candidate threshold set
+  // and tile-shape set
+  int best = 0, best_set = set_lo;
+  if (ncand > 1 || set_hi - set_lo > 1) {
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     for (int ci = 0; ci < ncand && rc == SPGEMM_OK; ++ci) {
       Candidate &cd = cands[ci];
-      if ((rc = upload(cd)) != SPGEMM_OK) break;
-      launch(static_cast<int64_t>(cd.items.size()));  // warm-up
-      (void)hipEventRecord(e0, s);
-      for (int rep = 0; rep < 3; ++rep) launch(static_cast<int64_t>(cd.items.size()));
-      (void)hipEventRecord(e1, s);
-      if (hipEventSynchronize(e1) != hipSuccess) rc = bfail(SPGEMM_EHIP, "autotune sync failed");
-      (void)hipEventElapsedTime(&cd.ms, e0, e1);
-      cd.ms /= 3.f;
-      if (ci == 0 || cd.ms < cands[best].ms) best = ci;
+      for (int set = set_lo; set < set_hi && rc == SPGEMM_OK; ++set) {
+        if ((rc = upload(cd, set)) != SPGEMM_OK) break;
+        int64_t off[kBatchNumClasses + 1];
+        class_ranges(cd.items[set], off);
+        enqueue(s, off, set);  // warm-up
+        (void)hipEventRecord(e0, s);
+        for (int rep = 0; rep < 3; ++rep) enqueue(s, off, set);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = bfail(SPGEMM_EHIP, "autotune sync failed");
+        (void)hipEventElapsedTime(&cd.ms[set], e0, e1);
+        cd.ms[set] /= 3.f;
+        if ((ci == 0 && set == set_lo) || cd.ms[set] < cands[best].ms[best_set]) {
+          best = ci;
+          best_set = set;
+        }
+      }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
-  if (rc == SPGEMM_OK) rc = upload(cands[best]);
+  if (rc == SPGEMM_OK) rc = upload(cands[best], best_set);
   if (rc != SPGEMM_OK) {
     for (auto &cd : cands) destroy_plans(cd.plans);
     spgemm_batch_destroy(b);
@@ -424,20 +455,21 @@ int spgemm_batch_create(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
   for (int ci = 0; ci < ncand; ++ci)
     if (ci != best) destroy_plans(cands[ci].plans);
   b->plans = cands[best].plans;
-  b->nitems = static_cast<int64_t>(cands[best].items.size());
+  b->nitems = static_cast<int64_t>(cands[best].items[best_set].size());
+  class_ranges(cands[best].items[best_set], b->cls_off);
+  b->shape_set = best_set;
 
-  // the replayable graph: queue reset + persistent kernel
+  // the replayable graph: one kernel node per nonempty class (no graph when
+  // every problem falls back to the plain path)
   hipStream_t cs = nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, cs, dhead);
-    if (b->nitems > 0)
-      hipLaunchKernelGGL(k_batch, dim3(b->grid), dim3(ESC_NT), 0, cs, ditems, b->nitems, dprob,
-                         dhead);
+  hipError_t e = hipSuccess;
+  if (b->nitems > 0) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess && cs) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess && cs) {
+    enqueue(cs, b->cls_off, b->shape_set);
     e = hipStreamEndCapture(cs, &b->graph);
   }
-  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e == hipSuccess && cs) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
   if (cs) (void)hipStreamDestroy(cs);
   if (e != hipSuccess) {
     spgemm_batch_destroy(b);
@@ -448,10 +480,13 @@ int spgemm_batch_create(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
   std::memset(&st, 0, sizeof(st));
   st.count = count;
   st.items = b->nitems;
-  st.grid = b->grid;
+  st.grid = 0;
+  for (int c = 0; c < kBatchNumClasses; ++c) st.grid += b->cls_off[c + 1] > b->cls_off[c];
   st.fallback = static_cast<int32_t>(b->fallback.size());
   std::memcpy(st.bin_edges, cands[best].edges, sizeof(st.bin_edges));
-  for (int ci = 0; ci < ncand && ci < 4; ++ci) st.tune_ms[ci] = cands[ci].ms;
+  st.shapes = best_set;
+  for (int ci = 0; ci < ncand && ci < 4; ++ci)
+    for (int set = 0; set < kBatchShapeSets; ++set) st.tune_ms[ci * kBatchShapeSets + set] = cands[ci].ms[set];
   for (int32_t p = 0; p < count; ++p) {
     spgemm_info I;
     spgemm_plan_info(b->plans[p], &I);
@@ -466,7 +501,7 @@ int spgemm_batch_create(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
 int spgemm_batch_run(spgemm_batch b, spgemm_csr_out *C, void *stream) {
   if (!b) return bfail(SPGEMM_EINVAL, "batch is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipError_t e = hipGraphLaunch(b->exec, s);
+  hipError_t e = b->exec ? hipGraphLaunch(b->exec, s) : hipSuccess;
   if (e != hipSuccess) return bfail(SPGEMM_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
   for (int32_t p : b->fallback) {
     // recompute into a fresh output, then move it into the batch's slot

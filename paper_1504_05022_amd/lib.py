@@ -48,7 +48,8 @@ class Options(ctypes.Structure):
                 ("pool_entries", ctypes.c_int64), ("validate", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("timing_mask", ctypes.c_int32),
                 ("tiny_heap", ctypes.c_int32), ("long_path", ctypes.c_int32),
-                ("long_direct", ctypes.c_int32)]
+                ("long_direct", ctypes.c_int32),
+                ("batch_shapes", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -72,14 +73,15 @@ class Info(ctypes.Structure):
 
 class BatchStats(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("fallback", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("shapes", ctypes.c_int32),
                 ("items", ctypes.c_int64), ("flops", ctypes.c_int64), ("nnz_c", ctypes.c_int64),
-                ("bin_edges", ctypes.c_int32 * 5), ("tune_ms", ctypes.c_float * 4)]
+                ("bin_edges", ctypes.c_int32 * 5), ("tune_ms", ctypes.c_float * 12)]
 
     def as_dict(self):
         return {"count": self.count, "fallback": self.fallback, "grid": self.grid,
-                "items": self.items, "flops": self.flops, "nnz_c": self.nnz_c,
-                "bin_edges": list(self.bin_edges), "tune_ms": list(self.tune_ms)}
+                "shapes": self.shapes, "items": self.items, "flops": self.flops,
+                "nnz_c": self.nnz_c, "bin_edges": list(self.bin_edges),
+                "tune_ms": list(self.tune_ms)}
 
 
 # exported symbols declared in include/spgemm.h

@@ -3,7 +3,7 @@
 Every C_p of a batch must equal the single-product path bit for bit (same
 structure, same values: both sum each row in ascending (column, product
 index) order), and the oracle to the usual componentwise bound.  Problems
-that the persistent kernel does not take (rows with more than 1024
+that the class kernels do not take (rows with more than 1024
 products) are recomputed with the single-product path and counted in the
 statistics.
 """
@@ -88,12 +88,15 @@ def test_batch_replay_recomputes_values():
 
 
 def test_batch_fixed_edges_no_tuning():
+    """Thresholds fixed by the caller: only the three tile-shape sets are
+    timed, under those thresholds."""
     import torch
     problems = S.config4(count=8, nmin=300, nmax=1500)
     dev, b = _batch(problems, bin_edges=[16, 64, 256, 512, 1024])
     st = b.stats.as_dict()
     assert st["bin_edges"] == [16, 64, 256, 512, 1024]
-    assert st["tune_ms"][1:] == [0.0, 0.0, 0.0]
+    assert all(t > 0 for t in st["tune_ms"][:3]) and st["tune_ms"][3:] == [0.0] * 9
+    assert st["shapes"] in (0, 1, 2)
     outs = b.run()
     torch.cuda.synchronize()
     for p, (A, B) in enumerate(problems):
@@ -171,4 +174,21 @@ def test_config4_full_batch_sampled():
             _oracle_check(A, B, h)
         if p % 4 == 0:
             _same(h, _plain(A, B))
+    b.close()
+
+
+@pytest.mark.parametrize("shapes", [1, 2, 3])
+def test_batch_every_tile_shape_set(shapes):
+    """Each tile-shape set (lanes per row against products per lane of every
+    capacity class), fixed by batch_shapes, gives C bit for bit equal to the
+    plain path; with the thresholds fixed too nothing is timed."""
+    import torch
+    problems = S.config4(count=12, nmin=300, nmax=3000)
+    dev, b = _batch(problems, bin_edges=[16, 64, 256, 512, 1024], batch_shapes=shapes)
+    st = b.stats.as_dict()
+    assert st["shapes"] == shapes - 1 and st["tune_ms"] == [0.0] * 12
+    outs = b.run()
+    torch.cuda.synchronize()
+    for p, (A, B) in enumerate(problems):
+        _same(outs[p].to_host(), _plain(A, B))
     b.close()
