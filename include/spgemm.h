@@ -291,6 +291,10 @@ typedef struct {
   int32_t bin_edges[5]; /* thresholds chosen by the autotuner                 */
   float tune_ms[12];    /* timed candidates (ms per run): threshold set t and
                            shape set k at [3 t + k]; 0 where not timed       */
+  int64_t bytes_scratch;/* spgemm_batch_multiply: most device memory it held
+                           at once besides the outputs (analysis arrays, C~,
+                           items, a fallback problem's plain-path peak); 0
+                           for a graph-replayed batch                        */
 } spgemm_batch_stats;
 
 /*
@@ -319,6 +323,36 @@ int spgemm_batch_stats_get(spgemm_batch batch, spgemm_batch_stats *stats);
 
 /* Release the graph, the plans and the outputs. */
 int spgemm_batch_destroy(spgemm_batch batch);
+
+/*
+ * One-shot batched products for problems seen once (no plan is kept):
+ * every stage for all `count` problems at once.  Stage 1 (Algorithm 2)
+ * runs over the concatenated entries and rows of every problem in single
+ * launches; one read-back of the per-problem row counts of each capacity
+ * class (2^c products, c = 0..10) sizes C~ with u_i entries per row (the
+ * hybrid allocation of Section 3.1) and the class lists (stage 2,
+ * Algorithm 3, with power-of-two bins); the wavefront ESC runs once per
+ * class over the rows of every problem; a scan of the row sizes and a
+ * second read-back size the outputs; one launch compacts every C_p
+ * (stage 5).  Problems with a row above 1024 products, or with
+ * n_p * 1024 >= 2^32, go through the plain path (spgemm_multiply) instead
+ * and are counted in stats->fallback.
+ *
+ * opt: checked as for spgemm_analyze; batch_shapes picks the tile-shape set
+ * (0 = set 0, the plain path's shapes; no autotuning here).  Outputs: C[p]
+ * (count entries) describe C_p, whose three arrays all lie in one device
+ * block from alloc_fn (hipMallocAsync when alloc_fn is NULL) returned in
+ * *out_mem; the caller owns it and releases every C_p at once with free_fn
+ * (hipFreeAsync).  *out_mem is NULL when count is 0 or on error (nothing
+ * stays allocated then).  Every C_p equals spgemm_multiply's bit for bit
+ * (same structure; each sum in the same (column, product index) order).
+ * Synchronizes `stream` twice; the scratch is released in stream order
+ * before returning.
+ */
+int spgemm_batch_multiply(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
+                          const spgemm_options *opt, spgemm_alloc_fn alloc_fn,
+                          spgemm_free_fn free_fn, void *ctx, void *stream, spgemm_csr_out *C,
+                          void **out_mem, spgemm_batch_stats *stats);
 
 /*
  * Merge-algorithm microbenchmark (Section 3.2, Fig. 5): merge `pairs`

@@ -8,6 +8,7 @@ from .lib import (  # noqa: F401
     Batch,
     CsrMatrix,
     Plan,
+    batch_multiply,
     SpgemmError,
     default_options,
     load,

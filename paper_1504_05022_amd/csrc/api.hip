@@ -1347,4 +1347,15 @@ const int64_t *plan_upper(spgemm_plan p) { return p->u; }
 int64_t *plan_rownnz(spgemm_plan p) { return p->rownnz; }
 const int32_t *plan_binlist(spgemm_plan p) { return p->binlist; }
 void set_last_error(const std::string &msg) { g_last_error = msg; }
+// the input checks of spgemm_analyze, for the batched forms
+int check_problem(const spgemm_csr *A, const spgemm_csr *B) {
+  int rc;
+  if ((rc = check_csr(A, "A")) != SPGEMM_OK) return rc;
+  if ((rc = check_csr(B, "B")) != SPGEMM_OK) return rc;
+  if (A->cols != B->rows)
+    return fail(SPGEMM_EINVAL, "inner dimensions differ (A.cols != B.rows)");
+  if (A->dtype != B->dtype) return fail(SPGEMM_EINVAL, "A and B have different dtypes");
+  return SPGEMM_OK;
+}
+int check_opts(const spgemm_options &o) { return check_options(o); }
 }  // namespace spg

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "esc_body.hpp"
+#include "stream_copy.hpp"
 
 namespace spg {
 
@@ -127,6 +128,180 @@ BatchKernel batch_kernel(int set, int c) {
   static const std::array<BatchKernel, kBatchNumClasses> k2 =
       batch_kernels_of<2>(std::make_integer_sequence<int, kBatchNumClasses>{});
   return set == 1 ? k1[c] : (set == 2 ? k2[c] : k0[c]);
+}
+
+// One launch per class over an item list grouped by ascending class (items
+// of class c at [off[c], off[c+1])), the largest rows first (their
+// work-groups run longest), one work-group per item.
+void launch_classes(hipStream_t st, const BatchItem *ditems, const BatchProblem *dprob,
+                    const int64_t (&off)[kBatchNumClasses + 1], int set) {
+  for (int c = kBatchNumClasses - 1; c >= 0; --c) {
+    const int64_t n = off[c + 1] - off[c];
+    if (n > 0)
+      hipLaunchKernelGGL(batch_kernel(set, c), dim3(static_cast<unsigned int>(n)), dim3(ESC_NT),
+                         0, st, ditems + off[c], dprob);
+  }
+}
+
+
+// ------------------------------------------------- one-shot batched product
+//
+// spgemm_batch_multiply runs every stage for many problems at once, without
+// a plan: stage 1 (Algorithm 2) over the concatenated entries and rows of
+// all problems, one read-back of the class counts, the hybrid allocation of
+// C~ (every row gets u_i entries, Section 3.1), the wavefront ESC per
+// capacity class, the scan of the row sizes and one compaction over all
+// problems.  Problems are cut into tiles of entries or rows, so that a
+// work-group never spans two problems.
+
+constexpr int BM_NT = 256;
+constexpr int BM_ENTRY_TILE = BM_NT * 16;       // entries of A_p per work-group
+constexpr int BM_ROW_TILE = BM_NT;              // rows per work-group
+constexpr int BM_NCLS = kBatchNumClasses + 1;   // capacity classes, then rows above 1024
+
+struct BmProblem {
+  const int32_t *arp, *acol, *brp;
+  int64_t m, nnz;       // rows and entries of A_p
+  int64_t eo, ro;       // the problem's first entry and first row in the concatenation
+  int32_t *crp, *ccol;  // C_p (set before the compaction)
+  void *cval;
+  const void *tval;     // C~ values of the problem, indexed by C~ offsets
+  int32_t dtype;
+  int32_t batched;      // 0: computed by the plain path instead
+};
+
+struct BmTile {
+  int32_t prob;
+  int32_t pad;
+  int64_t start;  // first entry or row of the tile in its problem
+};
+
+// capacity class of a row with u products: -1 for none, kBatchNumClasses
+// above the largest class
+__host__ __device__ inline int bm_class(int64_t u) {
+  if (u <= 0) return -1;
+  if (u > batch_class_cap(kBatchNumClasses - 1)) return kBatchNumClasses;
+  int c = 0;
+  while ((int64_t(1) << c) < u) ++c;
+  return c;
+}
+
+// Stage 1, products of every entry: w[e] = nnz(b_{col(e)*}).
+__global__ __launch_bounds__(BM_NT) void k_bm_entries(const BmTile *tiles, const BmProblem *probs,
+                                                      int32_t *w) {
+  const BmTile t = tiles[blockIdx.x];
+  const BmProblem &q = probs[t.prob];
+  const int32_t *acol = q.acol;
+  const int32_t *brp = q.brp;
+  const int64_t nnz = q.nnz;
+  int32_t *wp = w + q.eo;
+#pragma unroll
+  for (int j = 0; j < BM_ENTRY_TILE / BM_NT; ++j) {
+    const int64_t e = t.start + j * BM_NT + threadIdx.x;
+    if (e < nnz) {
+      const int32_t c = acol[e];
+      wp[e] = brp[c + 1] - brp[c];
+    }
+  }
+}
+
+// Stage 1, rows: u_i from the entry scan P, rows of every capacity class
+// and the sum of u_i counted per problem (one atomic per wavefront and
+// class).  Rows without products get their final size, 0, here.
+__global__ __launch_bounds__(BM_NT) void k_bm_rows(const BmTile *tiles, const BmProblem *probs,
+                                                   const int64_t *P, int64_t *U, int64_t *RN,
+                                                   unsigned long long *cnt,
+                                                   unsigned long long *sumu) {
+  const BmTile t = tiles[blockIdx.x];
+  const BmProblem &q = probs[t.prob];
+  const int64_t i = t.start + threadIdx.x;
+  const bool valid = i < q.m;
+  int64_t u = 0;
+  if (valid) {
+    u = P[q.eo + q.arp[i + 1]] - P[q.eo + q.arp[i]];
+    U[q.ro + i] = u;
+    if (u == 0) RN[q.ro + i] = 0;
+  }
+  const int c = valid ? bm_class(u) : -1;
+  unsigned long long *cp = cnt + static_cast<int64_t>(t.prob) * BM_NCLS;
+  for (int k = 0; k < BM_NCLS; ++k) {
+    const unsigned long long mk = __ballot(c == k);
+    if (mk != 0 && lane() == 0) atomicAdd(cp + k, static_cast<unsigned long long>(__popcll(mk)));
+  }
+  const long long tot = group_last<WAVE>(group_incl_sum<WAVE>(static_cast<long long>(u)));
+  if (tot != 0 && lane() == 0) atomicAdd(sumu + t.prob, static_cast<unsigned long long>(tot));
+}
+
+// Stage 2: the rows of every batched problem into its class lists; cur
+// holds the next free position of every (problem, class) list.  The order
+// within a list does not matter (every row goes to its own place in C~).
+__global__ __launch_bounds__(BM_NT) void k_bm_scatter(const BmTile *tiles, const BmProblem *probs,
+                                                      const int64_t *U, unsigned long long *cur,
+                                                      int32_t *list) {
+  const BmTile t = tiles[blockIdx.x];
+  const BmProblem &q = probs[t.prob];
+  if (!q.batched) return;
+  const int64_t i = t.start + threadIdx.x;
+  const int c = i < q.m ? bm_class(U[q.ro + i]) : -1;
+  unsigned long long *cp = cur + static_cast<int64_t>(t.prob) * BM_NCLS;
+  const unsigned long long below = (1ull << lane()) - 1ull;
+  for (int k = 0; k < kBatchNumClasses; ++k) {
+    const unsigned long long mk = __ballot(c == k);
+    if (mk == 0) continue;
+    unsigned long long b = 0;
+    if (lane() == 0) b = atomicAdd(cp + k, static_cast<unsigned long long>(__popcll(mk)));
+    b = static_cast<unsigned long long>(__shfl(static_cast<long long>(b), 0, WAVE));
+    if (c == k) list[b + __popcll(mk & below)] = static_cast<int32_t>(i);
+  }
+}
+
+// nnz(C_p) boundaries: g[p] = RO at the problem's first row, g[count] = RO's total.
+__global__ void k_bm_gather(const BmProblem *probs, int32_t count, const int64_t *RO, int64_t R,
+                            int64_t *g) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < count) g[p] = RO[probs[p].ro];
+  if (p == count) g[p] = RO[R];
+}
+
+template <typename T>
+DEVI void bm_copy_rows(const BmProblem &q, const int32_t *tcol, const int64_t *CTO,
+                       const int64_t *RO, const int64_t *RN, int64_t r0, int64_t end,
+                       CopyTable<CP_ROWS> &tb) {
+  const int64_t i = r0 + lane();
+  int64_t n = 0, src = 0, o = 0;
+  if (lane() < CP_ROWS && i < end) {
+    const int64_t base = RO[q.ro];
+    o = RO[q.ro + i] - base;
+    q.crp[i] = static_cast<int32_t>(o);
+    if (i == q.m - 1) q.crp[q.m] = static_cast<int32_t>(RO[q.ro + q.m] - base);
+    n = RN[q.ro + i];
+    src = CTO[q.ro + i];
+  }
+  wave_stream_copy<T, CP_ROWS>(n, tcol + src, static_cast<const T *>(q.tval) + src, o, q.ccol,
+                               static_cast<T *>(q.cval), tb);
+}
+
+// Stage 5 for every batched problem: row pointers of C_p and its rows
+// copied from C~, CP_ROWS rows per wavefront.
+__global__ __launch_bounds__(CP_NT) void k_bm_compact(const BmTile *tiles, const BmProblem *probs,
+                                                      const int32_t *tcol, const int64_t *CTO,
+                                                      const int64_t *RO, const int64_t *RN) {
+  __shared__ CopyTable<CP_ROWS> tabs[CP_NT / WAVE];
+  const BmTile t = tiles[blockIdx.x];
+  const BmProblem &q = probs[t.prob];
+  if (!q.batched) return;
+  if (q.m == 0) {
+    if (threadIdx.x == 0) q.crp[0] = 0;
+    return;
+  }
+  const int w = threadIdx.x / WAVE;
+  const int64_t end = min(t.start + BM_ROW_TILE, q.m);
+  for (int64_t r0 = t.start + w * CP_ROWS; r0 < end; r0 += (CP_NT / WAVE) * CP_ROWS) {
+    if (q.dtype == SPGEMM_F64)
+      bm_copy_rows<double>(q, tcol, CTO, RO, RN, r0, end, tabs[w]);
+    else
+      bm_copy_rows<float>(q, tcol, CTO, RO, RN, r0, end, tabs[w]);
+  }
 }
 
 }  // namespace spg
@@ -406,15 +581,8 @@ int spgemm_batch_create(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
     if (hipStreamSynchronize(s) != hipSuccess) return bfail(SPGEMM_EHIP, "upload sync failed");
     return SPGEMM_OK;
   };
-  // one launch per class, the largest rows first (their work-groups run
-  // longest), one work-group per item
   auto enqueue = [&](hipStream_t st, const int64_t (&off)[kBatchNumClasses + 1], int set) {
-    for (int c = kBatchNumClasses - 1; c >= 0; --c) {
-      const int64_t n = off[c + 1] - off[c];
-      if (n > 0)
-        hipLaunchKernelGGL(batch_kernel(set, c), dim3(static_cast<unsigned int>(n)), dim3(ESC_NT),
-                           0, st, ditems + off[c], static_cast<const BatchProblem *>(dprob));
-    }
+    launch_classes(st, ditems, dprob, off, set);
   };
 
   // autotuner: time the class launches under every candidate threshold set
@@ -538,6 +706,363 @@ int spgemm_batch_destroy(spgemm_batch b) {
   b->put(b->dmem, s);
   b->put(b->doff, s);
   delete b;
+  return SPGEMM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device memory of one spgemm_batch_multiply call, released on every exit
+// unless kept.
+struct BmMem {
+  spgemm_alloc_fn af;
+  spgemm_free_fn ff;
+  void *ctx;
+  hipStream_t s;
+  std::vector<void *> held;
+  void *get(size_t bytes) {
+    bytes = (bytes + 255) & ~static_cast<size_t>(255);
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (af) {
+      p = af(bytes, ctx, reinterpret_cast<void *>(s));
+    } else if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (p) held.push_back(p);
+    return p;
+  }
+  void put(void *p) {
+    if (!p) return;
+    if (ff)
+      ff(p, ctx, reinterpret_cast<void *>(s));
+    else
+      (void)hipFreeAsync(p, s);
+  }
+  void keep(void *p) { held.erase(std::remove(held.begin(), held.end(), p), held.end()); }
+  ~BmMem() {
+    for (void *p : held) put(p);
+  }
+};
+
+size_t round256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+}  // namespace
+
+extern "C" {
+
+int spgemm_batch_multiply(int32_t count, const spgemm_csr *A, const spgemm_csr *B,
+                          const spgemm_options *opt, spgemm_alloc_fn alloc_fn,
+                          spgemm_free_fn free_fn, void *ctx, void *stream, spgemm_csr_out *C,
+                          void **out_mem, spgemm_batch_stats *stats) {
+  if (!out_mem) return bfail(SPGEMM_EINVAL, "out_mem is NULL");
+  *out_mem = nullptr;
+  if (count < 0 || (count > 0 && (!A || !B || !C)))
+    return bfail(SPGEMM_EINVAL, "bad problem count or NULL arrays");
+  if ((alloc_fn == nullptr) != (free_fn == nullptr))
+    return bfail(SPGEMM_EINVAL, "alloc_fn and free_fn must both be set or both be NULL");
+  spgemm_options o;
+  spgemm_default_options(&o);
+  if (opt) o = *opt;
+  int rc = check_opts(o);
+  if (rc != SPGEMM_OK) return rc;
+  if (o.batch_shapes < 0 || o.batch_shapes > kBatchShapeSets)
+    return bfail(SPGEMM_EINVAL, "batch_shapes must be 0 (default shapes) or 1..3");
+  for (int32_t p = 0; p < count; ++p)
+    if ((rc = check_problem(&A[p], &B[p])) != SPGEMM_OK) return rc;
+  const int set = o.batch_shapes ? o.batch_shapes - 1 : 0;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  spgemm_batch_stats st;
+  std::memset(&st, 0, sizeof(st));
+  st.count = count;
+  st.shapes = set;
+  if (count == 0) {
+    if (stats) *stats = st;
+    return SPGEMM_OK;
+  }
+  BmMem mem{alloc_fn, free_fn, ctx, s, {}};
+
+  // the concatenation: entries and rows of every problem in turn, in tiles
+  std::vector<BmProblem> hp(count);
+  std::vector<BmTile> etile, rtile;
+  int64_t E = 0, R = 0;
+  for (int32_t p = 0; p < count; ++p) {
+    BmProblem &q = hp[p];
+    std::memset(&q, 0, sizeof(q));
+    q.arp = A[p].row_ptr;
+    q.acol = A[p].col_idx;
+    q.brp = B[p].row_ptr;
+    q.m = A[p].rows;
+    q.nnz = A[p].nnz;
+    q.eo = E;
+    q.ro = R;
+    q.dtype = A[p].dtype;
+    for (int64_t e = 0; e < q.nnz; e += BM_ENTRY_TILE) etile.push_back(BmTile{p, 0, e});
+    for (int64_t r = 0; r < std::max<int64_t>(q.m, 1); r += BM_ROW_TILE)
+      rtile.push_back(BmTile{p, 0, r});
+    E += q.nnz;
+    R += q.m;
+  }
+  if (etile.size() >= (size_t(1) << 31) || rtile.size() >= (size_t(1) << 31))
+    return bfail(SPGEMM_EOVERFLOW, "batch too large for one launch");
+
+  // scratch of the analysis
+  const int64_t ncnt = static_cast<int64_t>(count) * BM_NCLS;
+  size_t off = 0;
+  auto add = [&](size_t bytes) {
+    const size_t o0 = off;
+    off = round256(off + std::max<size_t>(bytes, 1));
+    return o0;
+  };
+  const size_t o_prob = add(sizeof(BmProblem) * count);
+  const size_t o_et = add(sizeof(BmTile) * etile.size());
+  const size_t o_rt = add(sizeof(BmTile) * rtile.size());
+  const size_t o_w = add(sizeof(int32_t) * E);
+  const size_t o_P = add(sizeof(int64_t) * (E + 1));
+  const size_t o_part = add(sizeof(int64_t) * scan_part_len(std::max<int64_t>(std::max(E, R), 1)));
+  const size_t o_U = add(sizeof(int64_t) * R);
+  const size_t o_CTO = add(sizeof(int64_t) * (R + 1));
+  const size_t o_RN = add(sizeof(int64_t) * R);
+  const size_t o_RO = add(sizeof(int64_t) * (R + 1));
+  const size_t o_cnt = add(sizeof(unsigned long long) * (ncnt + count));  // counts, then sums of u
+  const size_t o_cur = add(sizeof(unsigned long long) * ncnt);
+  const size_t o_list = add(sizeof(int32_t) * R);
+  const size_t o_g = add(sizeof(int64_t) * (count + 1));
+  const size_t o_bp = add(sizeof(BatchProblem) * count);
+  char *ws = static_cast<char *>(mem.get(off));
+  if (!ws) return bfail(SPGEMM_ENOMEM, "batch scratch allocation failed");
+  BmProblem *dprob = reinterpret_cast<BmProblem *>(ws + o_prob);
+  BmTile *det = reinterpret_cast<BmTile *>(ws + o_et);
+  BmTile *drt = reinterpret_cast<BmTile *>(ws + o_rt);
+  int32_t *dw = reinterpret_cast<int32_t *>(ws + o_w);
+  int64_t *dP = reinterpret_cast<int64_t *>(ws + o_P);
+  int64_t *dpart = reinterpret_cast<int64_t *>(ws + o_part);
+  int64_t *dU = reinterpret_cast<int64_t *>(ws + o_U);
+  int64_t *dCTO = reinterpret_cast<int64_t *>(ws + o_CTO);
+  int64_t *dRN = reinterpret_cast<int64_t *>(ws + o_RN);
+  int64_t *dRO = reinterpret_cast<int64_t *>(ws + o_RO);
+  unsigned long long *dcnt = reinterpret_cast<unsigned long long *>(ws + o_cnt);
+  unsigned long long *dsumu = dcnt + ncnt;
+  unsigned long long *dcur = reinterpret_cast<unsigned long long *>(ws + o_cur);
+  int32_t *dlist = reinterpret_cast<int32_t *>(ws + o_list);
+  int64_t *dg = reinterpret_cast<int64_t *>(ws + o_g);
+  BatchProblem *dbp = reinterpret_cast<BatchProblem *>(ws + o_bp);
+  int64_t bytes_scratch = static_cast<int64_t>(off);
+
+  auto h2d = [&](void *dst, const void *src, size_t bytes) {
+    return bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+  };
+  if (!h2d(dprob, hp.data(), sizeof(BmProblem) * count) ||
+      !h2d(det, etile.data(), sizeof(BmTile) * etile.size()) ||
+      !h2d(drt, rtile.data(), sizeof(BmTile) * rtile.size()))
+    return bfail(SPGEMM_EHIP, "batch table upload failed");
+  launch_zero(dcnt, sizeof(unsigned long long) * (ncnt + count), s);
+
+  // stage 1 over every problem: products per entry, their scan, u_i
+  if (!etile.empty())
+    hipLaunchKernelGGL(k_bm_entries, dim3(static_cast<unsigned int>(etile.size())), dim3(BM_NT),
+                       0, s, det, dprob, dw);
+  scan_i32(dw, E, dP, dpart, s);
+  hipLaunchKernelGGL(k_bm_rows, dim3(static_cast<unsigned int>(rtile.size())), dim3(BM_NT), 0, s,
+                     drt, dprob, dP, dU, dRN, dcnt, dsumu);
+  std::vector<unsigned long long> hcnt(ncnt + count);
+  if (hipMemcpyAsync(hcnt.data(), dcnt, sizeof(unsigned long long) * (ncnt + count),
+                     hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return bfail(SPGEMM_EHIP, std::string("batch analysis failed: ") +
+                                  hipGetErrorString(hipGetLastError()));
+
+  // problems of the batched kernels (rows up to 1024 products, 32-bit keys);
+  // C~ holds u_i entries for each of their rows (hybrid allocation)
+  std::vector<int32_t> fallback;
+  std::vector<int64_t> cbase(count, 0);
+  int64_t ntilde = 0;  // entries of C~
+  for (int32_t p = 0; p < count; ++p) {
+    const bool keys32 = (static_cast<uint64_t>(B[p].cols) << 10) <= 0xffffffffull;
+    hp[p].batched = keys32 && hcnt[static_cast<int64_t>(p) * BM_NCLS + kBatchNumClasses] == 0;
+    st.flops += 2 * static_cast<int64_t>(hcnt[ncnt + p]);
+    if (!hp[p].batched) {
+      fallback.push_back(p);
+      // no C~ entries and no row sizes for the rows of a fallback problem
+      if (hp[p].m > 0) {
+        launch_zero(dU + hp[p].ro, sizeof(int64_t) * hp[p].m, s);
+        launch_zero(dRN + hp[p].ro, sizeof(int64_t) * hp[p].m, s);
+      }
+      continue;
+    }
+    cbase[p] = ntilde;
+    ntilde += static_cast<int64_t>(hcnt[ncnt + p]);
+  }
+  // class lists grouped by class, then problem; items of at most 256 / G rows
+  std::vector<unsigned long long> hcur(ncnt, 0);
+  std::vector<BatchItem> items;
+  int64_t cls_off[kBatchNumClasses + 1];
+  {
+    int64_t pos = 0;
+    for (int c = 0; c < kBatchNumClasses; ++c) {
+      cls_off[c] = static_cast<int64_t>(items.size());
+      const int rpb = class_rpb(set, c);
+      for (int32_t p = 0; p < count; ++p) {
+        if (!hp[p].batched) continue;
+        const int64_t n = static_cast<int64_t>(hcnt[static_cast<int64_t>(p) * BM_NCLS + c]);
+        hcur[static_cast<int64_t>(p) * BM_NCLS + c] = static_cast<unsigned long long>(pos);
+        for (int64_t k = 0; k < n; k += rpb) {
+          BatchItem it;
+          it.prob = p;
+          it.cls = c;
+          it.start = pos + k;
+          it.count = static_cast<int32_t>(std::min<int64_t>(rpb, n - k));
+          it.pad = 0;
+          items.push_back(it);
+        }
+        pos += n;
+      }
+    }
+    cls_off[kBatchNumClasses] = static_cast<int64_t>(items.size());
+  }
+  for (int c = 0; c < kBatchNumClasses; ++c)
+    if (cls_off[c + 1] - cls_off[c] >= (int64_t(1) << 31))
+      return bfail(SPGEMM_EOVERFLOW, "batch too large for one launch");
+
+  // C~ (columns; values in 8-byte slots whatever the problem's type, so
+  // that binary32 and binary64 problems share one offset space) and items
+  char *tcol = static_cast<char *>(mem.get(std::max<int64_t>(ntilde, 1) * 4));
+  char *tval = static_cast<char *>(mem.get(std::max<int64_t>(ntilde, 1) * 8));
+  BatchItem *ditems = static_cast<BatchItem *>(mem.get(sizeof(BatchItem) * std::max<size_t>(items.size(), 1)));
+  if (!tcol || !tval || !ditems) return bfail(SPGEMM_ENOMEM, "C~ allocation failed");
+  bytes_scratch += static_cast<int64_t>(round256(std::max<int64_t>(ntilde, 1) * 4) +
+                                        round256(std::max<int64_t>(ntilde, 1) * 8) +
+                                        round256(sizeof(BatchItem) * std::max<size_t>(items.size(), 1)));
+  std::vector<BatchProblem> hbp(count);
+  for (int32_t p = 0; p < count; ++p) {
+    // a binary32 problem's values at slot offset cbase + k sit at byte
+    // 8 * cbase + 4 * k: inside its own slots
+    const size_t vs = A[p].dtype == SPGEMM_F64 ? 8 : 4;
+    hp[p].tval = tval + (8 - vs) * static_cast<size_t>(cbase[p]);
+    BatchProblem &q = hbp[p];
+    q.arp = A[p].row_ptr;
+    q.acol = A[p].col_idx;
+    q.aval = A[p].val;
+    q.brp = B[p].row_ptr;
+    q.bcol = B[p].col_idx;
+    q.bval = B[p].val;
+    q.P = dP + hp[p].eo;
+    q.u = dU + hp[p].ro;
+    q.rowoff = dCTO + hp[p].ro;
+    q.ccol = reinterpret_cast<int32_t *>(tcol);
+    q.cval = const_cast<void *>(hp[p].tval);
+    q.rownnz = dRN + hp[p].ro;
+    q.binlist = dlist;
+    q.dtype = A[p].dtype;
+    q.pad = 0;
+  }
+  if (!h2d(dprob, hp.data(), sizeof(BmProblem) * count) ||
+      !h2d(dbp, hbp.data(), sizeof(BatchProblem) * count) ||
+      !h2d(dcur, hcur.data(), sizeof(unsigned long long) * ncnt) ||
+      !h2d(ditems, items.data(), sizeof(BatchItem) * items.size()))
+    return bfail(SPGEMM_EHIP, "batch table upload failed");
+
+  // C~ offsets, class lists, the ESC per class, row sizes of C
+  scan_i64(dU, R, dCTO, dpart, s);
+  hipLaunchKernelGGL(k_bm_scatter, dim3(static_cast<unsigned int>(rtile.size())), dim3(BM_NT), 0,
+                     s, drt, dprob, dU, dcur, dlist);
+  launch_classes(s, ditems, dbp, cls_off, set);
+  scan_i64(dRN, R, dRO, dpart, s);
+  hipLaunchKernelGGL(k_bm_gather, dim3(static_cast<unsigned int>((count + 256) / 256)), dim3(256),
+                     0, s, dprob, count, dRO, R, dg);
+  std::vector<int64_t> hg(count + 1);
+  if (hipMemcpyAsync(hg.data(), dg, sizeof(int64_t) * (count + 1), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return bfail(SPGEMM_EHIP, std::string("batch numeric stage failed: ") +
+                                  hipGetErrorString(hipGetLastError()));
+
+  // fallback problems through the plain path (their outputs are moved into
+  // the output block below)
+  std::vector<spgemm_csr_out> fb(count);
+  struct FbGuard {
+    std::vector<spgemm_csr_out> &v;
+    BmMem &mem;
+    ~FbGuard() {
+      for (auto &c : v) {
+        mem.put(c.row_ptr);
+        mem.put(c.col_idx);
+        mem.put(c.val);
+      }
+    }
+  } fb_guard{fb, mem};
+  std::vector<int64_t> nnz(count, 0);
+  int64_t fb_scratch = 0;  // the largest plain-path peak, on top of what is held here
+  for (int32_t p : fallback) {
+    spgemm_info I;
+    if ((rc = spgemm_multiply(&A[p], &B[p], &o, alloc_fn, free_fn, ctx, stream, &fb[p], &I)) !=
+        SPGEMM_OK)
+      return rc;
+    nnz[p] = fb[p].nnz;
+    fb_scratch = std::max(fb_scratch, I.bytes_scratch);
+  }
+  bytes_scratch += fb_scratch;
+  for (int32_t p = 0; p < count; ++p) {
+    if (!hp[p].batched) continue;
+    nnz[p] = hg[p + 1] - hg[p];
+    if (nnz[p] >= (int64_t(1) << 31))
+      return bfail(SPGEMM_EOVERFLOW, "nnz(C) exceeds the int32 index range");
+  }
+
+  // one block for every output: row pointers, columns, values of each C_p
+  size_t obytes = 0;
+  std::vector<size_t> orp(count), ocol(count), oval(count);
+  for (int32_t p = 0; p < count; ++p) {
+    const size_t vs = A[p].dtype == SPGEMM_F64 ? 8 : 4;
+    orp[p] = obytes;
+    obytes += round256(sizeof(int32_t) * (hp[p].m + 1));
+    ocol[p] = obytes;
+    obytes += round256(sizeof(int32_t) * std::max<int64_t>(nnz[p], 1));
+    oval[p] = obytes;
+    obytes += round256(vs * std::max<int64_t>(nnz[p], 1));
+  }
+  char *ob = static_cast<char *>(mem.get(obytes));
+  if (!ob) return bfail(SPGEMM_ENOMEM, "output allocation failed");
+  for (int32_t p = 0; p < count; ++p) {
+    const size_t vs = A[p].dtype == SPGEMM_F64 ? 8 : 4;
+    C[p].rows = A[p].rows;
+    C[p].cols = B[p].cols;
+    C[p].nnz = nnz[p];
+    C[p].row_ptr = reinterpret_cast<int32_t *>(ob + orp[p]);
+    C[p].col_idx = reinterpret_cast<int32_t *>(ob + ocol[p]);
+    C[p].val = ob + oval[p];
+    C[p].dtype = A[p].dtype;
+    hp[p].crp = C[p].row_ptr;
+    hp[p].ccol = C[p].col_idx;
+    hp[p].cval = C[p].val;
+    if (!hp[p].batched) {
+      bool ok = hipMemcpyAsync(C[p].row_ptr, fb[p].row_ptr, sizeof(int32_t) * (hp[p].m + 1),
+                               hipMemcpyDeviceToDevice, s) == hipSuccess;
+      if (ok && nnz[p] > 0)
+        ok = hipMemcpyAsync(C[p].col_idx, fb[p].col_idx, sizeof(int32_t) * nnz[p],
+                            hipMemcpyDeviceToDevice, s) == hipSuccess &&
+             hipMemcpyAsync(C[p].val, fb[p].val, vs * nnz[p], hipMemcpyDeviceToDevice, s) ==
+                 hipSuccess;
+      if (!ok) return bfail(SPGEMM_EHIP, "output copy failed");
+    }
+  }
+  if (!h2d(dprob, hp.data(), sizeof(BmProblem) * count))
+    return bfail(SPGEMM_EHIP, "batch table upload failed");
+  hipLaunchKernelGGL(k_bm_compact, dim3(static_cast<unsigned int>(rtile.size())), dim3(CP_NT), 0,
+                     s, drt, dprob, reinterpret_cast<const int32_t *>(tcol), dCTO, dRO, dRN);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bfail(SPGEMM_EHIP, std::string("batch multiply: ") + hipGetErrorString(e));
+  mem.keep(ob);
+  *out_mem = ob;
+
+  st.fallback = static_cast<int32_t>(fallback.size());
+  st.items = static_cast<int64_t>(items.size());
+  for (int c = 0; c < kBatchNumClasses; ++c) st.grid += cls_off[c + 1] > cls_off[c];
+  for (int32_t p = 0; p < count; ++p) st.nnz_c += nnz[p];
+  st.bytes_scratch = bytes_scratch;
+  if (stats) *stats = st;
   return SPGEMM_OK;
 }
 

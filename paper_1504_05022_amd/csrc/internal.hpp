@@ -542,5 +542,8 @@ const int64_t *plan_upper(spgemm_plan p);
 int64_t *plan_rownnz(spgemm_plan p);
 const int32_t *plan_binlist(spgemm_plan p);
 void set_last_error(const std::string &msg);
+// input checks of spgemm_analyze (CSR shapes and dtypes; option ranges)
+int check_problem(const spgemm_csr *A, const spgemm_csr *B);
+int check_opts(const spgemm_options &o);
 
 }  // namespace spg

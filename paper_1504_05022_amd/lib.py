@@ -75,13 +75,14 @@ class BatchStats(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("shapes", ctypes.c_int32),
                 ("items", ctypes.c_int64), ("flops", ctypes.c_int64), ("nnz_c", ctypes.c_int64),
-                ("bin_edges", ctypes.c_int32 * 5), ("tune_ms", ctypes.c_float * 12)]
+                ("bin_edges", ctypes.c_int32 * 5), ("tune_ms", ctypes.c_float * 12),
+                ("bytes_scratch", ctypes.c_int64)]
 
     def as_dict(self):
         return {"count": self.count, "fallback": self.fallback, "grid": self.grid,
                 "shapes": self.shapes, "items": self.items, "flops": self.flops,
                 "nnz_c": self.nnz_c, "bin_edges": list(self.bin_edges),
-                "tune_ms": list(self.tune_ms)}
+                "tune_ms": list(self.tune_ms), "bytes_scratch": self.bytes_scratch}
 
 
 # exported symbols declared in include/spgemm.h
@@ -89,7 +90,8 @@ EXPORTS = ("spgemm_default_options", "spgemm_strerror", "spgemm_last_error", "sp
            "spgemm_compute", "spgemm_backward", "spgemm_backward_static", "spgemm_plan_info",
            "spgemm_plan_destroy",
            "spgemm_batch_create", "spgemm_batch_run", "spgemm_batch_stats_get",
-           "spgemm_batch_destroy", "spgemm_merge_pairs", "spgemm_multiply")
+           "spgemm_batch_destroy", "spgemm_batch_multiply", "spgemm_merge_pairs",
+           "spgemm_multiply")
 
 _ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -160,6 +162,11 @@ def load(path: str = LIB_PATH):
     lib.spgemm_batch_stats_get.restype = ctypes.c_int
     lib.spgemm_batch_destroy.argtypes = [P]
     lib.spgemm_batch_destroy.restype = ctypes.c_int
+    lib.spgemm_batch_multiply.argtypes = [ctypes.c_int32, ctypes.POINTER(CsrDesc),
+                                          ctypes.POINTER(CsrDesc), ctypes.POINTER(Options),
+                                          _ALLOC_T, _FREE_T, P, P, ctypes.POINTER(CsrOut),
+                                          ctypes.POINTER(P), ctypes.POINTER(BatchStats)]
+    lib.spgemm_batch_multiply.restype = ctypes.c_int
     lib.spgemm_merge_pairs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_int, P, P, P, P, P]
     lib.spgemm_merge_pairs.restype = ctypes.c_int
@@ -426,3 +433,38 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def batch_multiply(pairs, options: Options | None = None, return_stats=False, **kw):
+    """Every C_p = A_p * B_p of ``pairs`` (list of (A_p, B_p) CsrMatrix
+    pairs, binary32 and binary64 mixed) in one spgemm_batch_multiply call:
+    no plan is kept.  The outputs are views into one device block, which
+    lives as long as any of them."""
+    lib = load()
+    pairs = list(pairs)
+    n = len(pairs)
+    da = (CsrDesc * max(n, 1))(*[a.desc() for a, _ in pairs])
+    db = (CsrDesc * max(n, 1))(*[b.desc() for _, b in pairs])
+    opts = options if options is not None else default_options(**kw)
+    outs = (CsrOut * max(n, 1))()
+    mem = ctypes.c_void_p()
+    st = BatchStats()
+    _check(lib.spgemm_batch_multiply(n, da, db, ctypes.byref(opts), _alloc_cb, _free_cb, None,
+                                     _stream_handle(), outs, ctypes.byref(mem), ctypes.byref(st)))
+    res = []
+    if mem.value:
+        block = _live.pop(mem.value)
+        base = mem.value
+        for p in range(n):
+            o = outs[p]
+            m, nnz = int(o.rows), int(o.nnz)
+            vt = torch.float64 if o.dtype == F64 else torch.float32
+
+            def part(ptr, nbytes, dt):
+                off = ptr - base
+                return block[off:off + nbytes].view(dt)
+
+            res.append(CsrMatrix((m, int(o.cols)), part(o.row_ptr, 4 * (m + 1), torch.int32),
+                                 part(o.col_idx, 4 * nnz, torch.int32),
+                                 part(o.val, vt.itemsize * nnz, vt)))
+    return (res, st) if return_stats else res

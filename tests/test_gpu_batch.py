@@ -192,3 +192,128 @@ def test_batch_every_tile_shape_set(shapes):
     for p, (A, B) in enumerate(problems):
         _same(outs[p].to_host(), _plain(A, B))
     b.close()
+
+
+# ---- one-shot batched products (spgemm_batch_multiply): no plan, no graph
+
+
+def _multiply(problems, **opts):
+    from paper_1504_05022_amd import CsrMatrix, batch_multiply
+    dev = [(CsrMatrix.from_host(A), CsrMatrix.from_host(B)) for A, B in problems]
+    outs, st = batch_multiply(dev, return_stats=True, **opts)
+    return dev, outs, st.as_dict()
+
+
+def test_batch_multiply_against_plain_and_oracle():
+    import torch
+    problems = S.config4(count=40, nmin=200, nmax=3000)
+    print("case: one-shot batch, 40 problems, n in [200, 3000]", flush=True)
+    dev, outs, st = _multiply(problems)
+    print("  stats", st, flush=True)
+    torch.cuda.synchronize()
+    assert st["count"] == 40 and st["fallback"] == 0 and st["items"] > 0
+    assert 0 < st["grid"] <= 11 and st["shapes"] == 0
+    flops = 0
+    for p, (A, B) in enumerate(problems):
+        h = outs[p].to_host()
+        assert outs[p].dtype == (torch.float64 if p % 2 == 0 else torch.float32)
+        _same(h, _plain(A, B))
+        if p % 5 == 0:
+            _oracle_check(A, B, h)
+        flops += oracle.upper_bound(A.as_tuple(), B.as_tuple())[1] * 2
+    assert st["flops"] == flops
+    assert st["nnz_c"] == sum(o.nnz for o in outs)
+    # scratch: at least C~ (4 + 8 bytes per product) and the entry scan
+    nprod = flops // 2
+    nnz_a = sum(A.nnz for A, _ in problems)
+    assert st["bytes_scratch"] >= 12 * nprod + 12 * nnz_a
+
+
+@pytest.mark.parametrize("shapes", [1, 2, 3])
+def test_batch_multiply_every_tile_shape_set(shapes):
+    import torch
+    problems = S.config4(count=10, nmin=300, nmax=2500)
+    dev, outs, st = _multiply(problems, batch_shapes=shapes)
+    torch.cuda.synchronize()
+    assert st["shapes"] == shapes - 1
+    for p, (A, B) in enumerate(problems):
+        _same(outs[p].to_host(), _plain(A, B))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_batch_multiply_fallback_and_degenerate_problems(dtype):
+    """Long rows (plain path, moved into the output block), no rows, only
+    empty rows, an all-zero A, 1x1, duplicates-heavy rows, next to ordinary
+    problems."""
+    import torch
+    from tests.helpers import from_rows, identity
+    longp = S.crafted_rows([5, 1500, 3000, 0, 17], n=2048, dtype=dtype)
+    empty_rows = (S.Csr(0, 50, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0, dtype)),
+                  S.Csr(50, 40, np.zeros(51, np.int32), np.zeros(0, np.int32), np.zeros(0, dtype)))
+    zero_a = S.Csr(30, 60, np.zeros(31, np.int32), np.zeros(0, np.int32), np.zeros(0, dtype))
+    one = from_rows(1, 1, [(0, 0, 3.0)], dtype)
+    crowded = S.crafted_rows([1024, 1000, 600, 1, 0, 2, 513], n=700, dtype=dtype, col_range=40)
+    problems = [S.config4(count=2, nmin=500, nmax=800)[0], longp, empty_rows,
+                (zero_a, identity(60, dtype)), (one, one), crowded,
+                S.config4(count=2, nmin=500, nmax=800)[1]]
+    print("case: one-shot fallback + degenerate problems,", dtype, flush=True)
+    dev, outs, st = _multiply(problems)
+    print("  stats", st, flush=True)
+    torch.cuda.synchronize()
+    assert st["fallback"] == 1
+    for p, (A, B) in enumerate(problems):
+        h = outs[p].to_host()
+        assert outs[p].shape == (A.rows, B.cols)
+        _oracle_check(A, B, h)
+        _same(h, _plain(A, B))
+
+
+def test_batch_multiply_only_fallbacks_and_empty():
+    import torch
+    from paper_1504_05022_amd import batch_multiply
+    outs, st = batch_multiply([], return_stats=True)
+    assert outs == [] and st.count == 0 and st.items == 0
+    problems = [S.crafted_rows([2000, 1100], n=4096), S.crafted_rows([1025], n=2048)]
+    dev, outs, st = _multiply(problems)
+    torch.cuda.synchronize()
+    assert st["fallback"] == 2 and st["items"] == 0 and st["grid"] == 0
+    for p, (A, B) in enumerate(problems):
+        _same(outs[p].to_host(), _plain(A, B))
+
+
+def test_batch_multiply_errors():
+    import ctypes
+    from paper_1504_05022_amd import SpgemmError
+    from paper_1504_05022_amd import lib as L
+    L.load()
+    mem = ctypes.c_void_p()
+    rc = L._lib.spgemm_batch_multiply(-1, None, None, None, L._alloc_cb, L._free_cb, None,
+                                      L._stream_handle(), None, ctypes.byref(mem), None)
+    assert rc == -1 and not mem
+    rc = L._lib.spgemm_batch_multiply(0, None, None, None, L._alloc_cb, L._free_cb, None,
+                                      L._stream_handle(), None, None, None)
+    assert rc == -1
+    A = S.Csr(4, 5, np.arange(5, dtype=np.int32), np.zeros(4, np.int32), np.ones(4))
+    with pytest.raises(SpgemmError):
+        _multiply([(A, A)])
+    good = S.config4(count=2, nmin=100, nmax=200)
+    with pytest.raises(SpgemmError):
+        _multiply(good, batch_shapes=4)
+
+
+def test_config4_full_batch_multiply_sampled():
+    """Workload 4 at full size through the one-shot form: every fourth
+    problem against the single-product path, 16 against the oracle."""
+    import torch
+    problems = S.config4()
+    dev, outs, st = _multiply(problems)
+    print("  stats", st, flush=True)
+    torch.cuda.synchronize()
+    assert st["fallback"] == 0
+    pick = set(range(0, 512, 32))
+    for p, (A, B) in enumerate(problems):
+        h = outs[p].to_host()
+        if p in pick:
+            _oracle_check(A, B, h)
+        if p % 4 == 0:
+            _same(h, _plain(A, B))
