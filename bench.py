@@ -76,6 +76,9 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 4 device-to-device copies of MIB MiB (the calibration "
                          "kernel for the HBM byte counters) and exit")
+    ap.add_argument("--diff-forward", action="store_true",
+                    help="only run the forward product of the differentiable workload "
+                         "(2 warm-up, 3 timed; the command its kernel profiles come from)")
     return ap.parse_args()
 
 
@@ -97,10 +100,8 @@ def copy_probe(mib):
 # figures stay valid only while these are unchanged
 _CSRC = "paper_1504_05022_amd/csrc/"
 KERNEL_SOURCES = {
-    "merge": (_CSRC + "long.hip", _CSRC + "common.hpp", _CSRC + "internal.hpp", _CSRC + "radix.hpp",
-              "include/spgemm.h"),
-    "window": (_CSRC + "window.hip", _CSRC + "common.hpp", _CSRC + "internal.hpp",
-               "include/spgemm.h"),
+    "merge": (_CSRC + "long.hip", _CSRC + "common.hpp", _CSRC + "internal.hpp", _CSRC + "radix.hpp"),
+    "window": (_CSRC + "window.hip", _CSRC + "common.hpp", _CSRC + "internal.hpp"),
 }
 
 
@@ -607,10 +608,41 @@ def parallel_oracle(n):
             "equal flops, one process each (slowest block %.2f s)" % (len(blocks), t)}
 
 
+def diff_forward():
+    """The differentiable workload's forward product alone (A 500000^2 power
+    law x B 500000x4096, binary32, default options)."""
+    import torch
+
+    import synthetic as S
+    from paper_1504_05022_amd import lib as L
+
+    L.load()
+    torch.cuda.set_device(0)
+    A, B = S.config5()
+    dA, dB = L.CsrMatrix.from_host(A), L.CsrMatrix.from_host(B)
+    del A, B
+    for _ in range(2):
+        C = L.spgemm(dA, dB)
+        del C
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        C, info = L.spgemm(dA, dB, return_info=True)
+        del C
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / 3
+    print(json.dumps({"workload": "A 500000^2 power law (2.2, mean 20) x B 500000x4096 (32/row), "
+                                  "FP32", "forward_ms": round(ms, 3), "flops": int(info.flops)}),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.diff_forward:
+        diff_forward()
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

@@ -255,6 +255,31 @@ __global__ __launch_bounds__(BM_NT) void k_bm_scatter(const BmTile *tiles, const
   }
 }
 
+// Work items of list (problem, class) = blockIdx.x: rows [base + k * rpb,
+// + rpb) of the class list from item io on (io < 0: no items); runs before
+// k_bm_scatter advances the list cursors past the bases.
+__global__ __launch_bounds__(BM_NT) void k_bm_items(const unsigned long long *cnt,
+                                                    const unsigned long long *base,
+                                                    const int64_t *io, int set,
+                                                    BatchItem *items) {
+  const int64_t k = blockIdx.x;
+  const int64_t first = io[k];
+  if (first < 0) return;
+  const int c = static_cast<int>(k % BM_NCLS);
+  const int rpb = ESC_NT / batch_class_g(set, c);
+  const int64_t n = static_cast<int64_t>(cnt[k]);
+  const int64_t b = static_cast<int64_t>(base[k]);
+  for (int64_t j = threadIdx.x; j * rpb < n; j += BM_NT) {
+    BatchItem it;
+    it.prob = static_cast<int32_t>(k / BM_NCLS);
+    it.cls = c;
+    it.start = b + j * rpb;
+    it.count = static_cast<int32_t>(min<int64_t>(rpb, n - j * rpb));
+    it.pad = 0;
+    items[first + j] = it;
+  }
+}
+
 // nnz(C_p) boundaries: g[p] = RO at the problem's first row, g[count] = RO's total.
 __global__ void k_bm_gather(const BmProblem *probs, int32_t count, const int64_t *RO, int64_t R,
                             int64_t *g) {
@@ -828,6 +853,7 @@ int spgemm_batch_multiply(int32_t count, const spgemm_csr *A, const spgemm_csr *
   const size_t o_RO = add(sizeof(int64_t) * (R + 1));
   const size_t o_cnt = add(sizeof(unsigned long long) * (ncnt + count));  // counts, then sums of u
   const size_t o_cur = add(sizeof(unsigned long long) * ncnt);
+  const size_t o_io = add(sizeof(int64_t) * ncnt);
   const size_t o_list = add(sizeof(int32_t) * R);
   const size_t o_g = add(sizeof(int64_t) * (count + 1));
   const size_t o_bp = add(sizeof(BatchProblem) * count);
@@ -846,6 +872,7 @@ int spgemm_batch_multiply(int32_t count, const spgemm_csr *A, const spgemm_csr *
   unsigned long long *dcnt = reinterpret_cast<unsigned long long *>(ws + o_cnt);
   unsigned long long *dsumu = dcnt + ncnt;
   unsigned long long *dcur = reinterpret_cast<unsigned long long *>(ws + o_cur);
+  int64_t *dio = reinterpret_cast<int64_t *>(ws + o_io);
   int32_t *dlist = reinterpret_cast<int32_t *>(ws + o_list);
   int64_t *dg = reinterpret_cast<int64_t *>(ws + o_g);
   BatchProblem *dbp = reinterpret_cast<BatchProblem *>(ws + o_bp);
@@ -895,32 +922,28 @@ int spgemm_batch_multiply(int32_t count, const spgemm_csr *A, const spgemm_csr *
     cbase[p] = ntilde;
     ntilde += static_cast<int64_t>(hcnt[ncnt + p]);
   }
-  // class lists grouped by class, then problem; items of at most 256 / G rows
+  // class lists grouped by class, then problem; items of at most 256 / G
+  // rows, written on the device from each list's first item (-1: none)
   std::vector<unsigned long long> hcur(ncnt, 0);
-  std::vector<BatchItem> items;
+  std::vector<int64_t> hio(ncnt, -1);
   int64_t cls_off[kBatchNumClasses + 1];
+  int64_t nitems = 0;
   {
     int64_t pos = 0;
     for (int c = 0; c < kBatchNumClasses; ++c) {
-      cls_off[c] = static_cast<int64_t>(items.size());
+      cls_off[c] = nitems;
       const int rpb = class_rpb(set, c);
       for (int32_t p = 0; p < count; ++p) {
         if (!hp[p].batched) continue;
-        const int64_t n = static_cast<int64_t>(hcnt[static_cast<int64_t>(p) * BM_NCLS + c]);
-        hcur[static_cast<int64_t>(p) * BM_NCLS + c] = static_cast<unsigned long long>(pos);
-        for (int64_t k = 0; k < n; k += rpb) {
-          BatchItem it;
-          it.prob = p;
-          it.cls = c;
-          it.start = pos + k;
-          it.count = static_cast<int32_t>(std::min<int64_t>(rpb, n - k));
-          it.pad = 0;
-          items.push_back(it);
-        }
+        const int64_t k = static_cast<int64_t>(p) * BM_NCLS + c;
+        const int64_t n = static_cast<int64_t>(hcnt[k]);
+        hcur[k] = static_cast<unsigned long long>(pos);
+        if (n > 0) hio[k] = nitems;
+        nitems += (n + rpb - 1) / rpb;
         pos += n;
       }
     }
-    cls_off[kBatchNumClasses] = static_cast<int64_t>(items.size());
+    cls_off[kBatchNumClasses] = nitems;
   }
   for (int c = 0; c < kBatchNumClasses; ++c)
     if (cls_off[c + 1] - cls_off[c] >= (int64_t(1) << 31))
@@ -930,11 +953,12 @@ int spgemm_batch_multiply(int32_t count, const spgemm_csr *A, const spgemm_csr *
   // that binary32 and binary64 problems share one offset space) and items
   char *tcol = static_cast<char *>(mem.get(std::max<int64_t>(ntilde, 1) * 4));
   char *tval = static_cast<char *>(mem.get(std::max<int64_t>(ntilde, 1) * 8));
-  BatchItem *ditems = static_cast<BatchItem *>(mem.get(sizeof(BatchItem) * std::max<size_t>(items.size(), 1)));
+  BatchItem *ditems =
+      static_cast<BatchItem *>(mem.get(sizeof(BatchItem) * std::max<int64_t>(nitems, 1)));
   if (!tcol || !tval || !ditems) return bfail(SPGEMM_ENOMEM, "C~ allocation failed");
   bytes_scratch += static_cast<int64_t>(round256(std::max<int64_t>(ntilde, 1) * 4) +
                                         round256(std::max<int64_t>(ntilde, 1) * 8) +
-                                        round256(sizeof(BatchItem) * std::max<size_t>(items.size(), 1)));
+                                        round256(sizeof(BatchItem) * std::max<int64_t>(nitems, 1)));
   std::vector<BatchProblem> hbp(count);
   for (int32_t p = 0; p < count; ++p) {
     // a binary32 problem's values at slot offset cbase + k sit at byte
@@ -961,8 +985,10 @@ int spgemm_batch_multiply(int32_t count, const spgemm_csr *A, const spgemm_csr *
   if (!h2d(dprob, hp.data(), sizeof(BmProblem) * count) ||
       !h2d(dbp, hbp.data(), sizeof(BatchProblem) * count) ||
       !h2d(dcur, hcur.data(), sizeof(unsigned long long) * ncnt) ||
-      !h2d(ditems, items.data(), sizeof(BatchItem) * items.size()))
+      !h2d(dio, hio.data(), sizeof(int64_t) * ncnt))
     return bfail(SPGEMM_EHIP, "batch table upload failed");
+  hipLaunchKernelGGL(k_bm_items, dim3(static_cast<unsigned int>(ncnt)), dim3(BM_NT), 0, s, dcnt,
+                     dcur, dio, set, ditems);
 
   // C~ offsets, class lists, the ESC per class, row sizes of C
   scan_i64(dU, R, dCTO, dpart, s);
@@ -1058,7 +1084,7 @@ int spgemm_batch_multiply(int32_t count, const spgemm_csr *A, const spgemm_csr *
   *out_mem = ob;
 
   st.fallback = static_cast<int32_t>(fallback.size());
-  st.items = static_cast<int64_t>(items.size());
+  st.items = nitems;
   for (int c = 0; c < kBatchNumClasses; ++c) st.grid += cls_off[c + 1] > cls_off[c];
   for (int32_t p = 0; p < count; ++p) st.nnz_c += nnz[p];
   st.bytes_scratch = bytes_scratch;
