@@ -48,18 +48,23 @@ template <int C> DEVI int64_t xcd_block_id() {
 
 // ---------------------------------------------------------------- shuffles
 
-// Value of lane (lane ^ m).  With m known at compile time, distances 1, 2
-// and 8 are DPP moves inside the VALU (quad permutations and a rotation of
-// each row of 16 lanes by 8), 4 and 16 are LDS-unit swizzles inside groups of
-// 32 lanes (no address operand), 32 goes through ds_bpermute.
+// Value of lane (lane ^ m).  With m known at compile time, masks 1, 2, 3, 7,
+// 8 and 15 are DPP moves inside the VALU (quad permutations, the mirror of
+// each half row of 8 and of each row of 16 lanes, a rotation of each row by
+// 8), 4, 16 and 31 are LDS-unit swizzles inside groups of 32 lanes (no
+// address operand), others go through ds_bpermute.
 DEVI uint32_t shfl_xor_u32(uint32_t v, int m) {
   const int x = static_cast<int>(v);
   switch (m) {
     case 1: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
     case 2: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
+    case 3: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x1B, 0xF, 0xF, false));
+    case 7: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false));
     case 8: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));
+    case 15: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false));
     case 4: return static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(x, 0x1F | (4 << 10)));
     case 16: return static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(x, 0x1F | (16 << 10)));
+    case 31: return static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(x, 0x1F | (31 << 10)));
     default: return static_cast<uint32_t>(__shfl_xor(x, m, WAVE));
   }
 }
@@ -263,20 +268,90 @@ DEVI void stage_lanes(Key (&k)[K], int pos, int size, int stride) {
   }
 }
 
+// The same network with every comparison ascending: each merge of two
+// sorted halves of a block of `size` starts by comparing element i with its
+// mirror i ^ (size - 1) (which leaves two bitonic halves, every key of the
+// first at most every key of the second), then halves them with strides
+// size/4 .. 1.  No comparison depends on a lane's block direction, so the
+// register stages need no selects and the lane stages one per key.
+template <int K, typename Key> DEVI void cas_asc(Key &a, Key &b) {
+  const Key lo = a < b ? a : b;
+  const Key hi = a < b ? b : a;
+  a = lo;
+  b = hi;
+}
+
+// Partner kk ^ M in registers (M < K), the lower index keeping the minimum.
+template <int K, int M, typename Key> DEVI void flip_regs(Key (&k)[K]) {
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int p = kk ^ M;
+    if (p > kk) cas_asc<K, Key>(k[kk], k[p]);
+  }
+}
+
+// STRIDE >= K: partner lane pos ^ (STRIDE / K), same register.
+template <int K, int STRIDE, typename Key> DEVI void half_lanes(Key (&k)[K], int pos) {
+  constexpr int PM = STRIDE / K;
+  const bool lower = (pos & PM) == 0;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const Key other = shfl_xor_key<Key>(k[kk], PM);
+    const Key mn = k[kk] < other ? k[kk] : other;
+    const Key mx = k[kk] < other ? other : k[kk];
+    k[kk] = lower ? mn : mx;
+  }
+}
+
+// Mirror of a block of SIZE >= 2K: partner lane pos ^ (SIZE / K - 1),
+// register K - 1 - kk.
+template <int K, int SIZE, typename Key> DEVI void mirror_lanes(Key (&k)[K], int pos) {
+  constexpr int PM = SIZE / K - 1;
+  const bool lower = (pos & (SIZE / (2 * K))) == 0;
+  if constexpr (K == 1) {  // the register is its own mirror
+    const Key o = shfl_xor_key<Key>(k[0], PM);
+    k[0] = lower ? (k[0] < o ? k[0] : o) : (k[0] < o ? o : k[0]);
+    return;
+  }
+  // registers kk and K - 1 - kk trade partners: two at a time, so that only
+  // two received keys are live at once
+#pragma unroll
+  for (int kk = 0; kk < K / 2; ++kk) {
+    const Key oa = shfl_xor_key<Key>(k[K - 1 - kk], PM);
+    const Key ob = shfl_xor_key<Key>(k[kk], PM);
+    const Key a = k[kk], b = k[K - 1 - kk];
+    k[kk] = lower ? (a < oa ? a : oa) : (a < oa ? oa : a);
+    k[K - 1 - kk] = lower ? (b < ob ? b : ob) : (b < ob ? ob : b);
+  }
+}
+
+// The halving stages STRIDE, STRIDE / 2, .. 1 of one merge.
+template <int K, int STRIDE, typename Key> DEVI void half_stages(Key (&k)[K], int pos) {
+  if constexpr (STRIDE > 0) {
+    if constexpr (STRIDE < K)
+      flip_regs<K, STRIDE, Key>(k);
+    else
+      half_lanes<K, STRIDE, Key>(k, pos);
+    half_stages<K, STRIDE / 2, Key>(k, pos);
+  }
+}
+
+// Merges of blocks of SIZE, 2 SIZE, .. N (each instantiated, so that every
+// stride and partner is a constant).
+template <int N, int K, int SIZE, typename Key> DEVI void merges_from(Key (&k)[K], int pos) {
+  if constexpr (SIZE <= N) {
+    if constexpr (SIZE <= K)
+      flip_regs<K, SIZE - 1, Key>(k);
+    else
+      mirror_lanes<K, SIZE, Key>(k, pos);
+    half_stages<K, SIZE / 4, Key>(k, pos);
+    merges_from<N, K, SIZE * 2, Key>(k, pos);
+  }
+}
+
 // Sort G*K keys held by an aligned group of G lanes (G <= 64).
 template <int G, int K, typename Key> DEVI void group_bitonic_sort(Key (&k)[K]) {
-  constexpr int N = G * K;
-  const int pos = lane() & (G - 1);
-#pragma unroll
-  for (int size = 2; size <= N; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      if (stride < K)
-        stage_regs<K, Key>(k, pos, size, stride);
-      else
-        stage_lanes<K, Key>(k, pos, size, stride);
-    }
-  }
+  merges_from<G * K, K, 2, Key>(k, lane() & (G - 1));
 }
 
 // Sort NT*K keys held by a work-group of NT threads.  Strides that cross
