@@ -290,17 +290,30 @@ template <int K, int M, typename Key> DEVI void flip_regs(Key (&k)[K]) {
   }
 }
 
+// The key a lane keeps from (own, partner's): the minimum in the lower lane,
+// the maximum in the upper.  For 32-bit keys that is the median of the two
+// and a per-lane bound (0 in the lower lane, all ones in the upper), one
+// VALU instruction instead of min, max and a select.
+template <typename Key> DEVI Key keep_of(Key own, Key other, bool lower, Key bound) {
+  if constexpr (sizeof(Key) == 4) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(own), "v"(other), "v"(bound));
+    return r;
+  } else {
+    const Key mn = own < other ? own : other;
+    const Key mx = own < other ? other : own;
+    return lower ? mn : mx;
+  }
+}
+
 // STRIDE >= K: partner lane pos ^ (STRIDE / K), same register.
 template <int K, int STRIDE, typename Key> DEVI void half_lanes(Key (&k)[K], int pos) {
   constexpr int PM = STRIDE / K;
   const bool lower = (pos & PM) == 0;
+  const Key bound = lower ? Key(0) : ~Key(0);
 #pragma unroll
-  for (int kk = 0; kk < K; ++kk) {
-    const Key other = shfl_xor_key<Key>(k[kk], PM);
-    const Key mn = k[kk] < other ? k[kk] : other;
-    const Key mx = k[kk] < other ? other : k[kk];
-    k[kk] = lower ? mn : mx;
-  }
+  for (int kk = 0; kk < K; ++kk)
+    k[kk] = keep_of<Key>(k[kk], shfl_xor_key<Key>(k[kk], PM), lower, bound);
 }
 
 // Mirror of a block of SIZE >= 2K: partner lane pos ^ (SIZE / K - 1),
@@ -308,9 +321,9 @@ template <int K, int STRIDE, typename Key> DEVI void half_lanes(Key (&k)[K], int
 template <int K, int SIZE, typename Key> DEVI void mirror_lanes(Key (&k)[K], int pos) {
   constexpr int PM = SIZE / K - 1;
   const bool lower = (pos & (SIZE / (2 * K))) == 0;
+  const Key bound = lower ? Key(0) : ~Key(0);
   if constexpr (K == 1) {  // the register is its own mirror
-    const Key o = shfl_xor_key<Key>(k[0], PM);
-    k[0] = lower ? (k[0] < o ? k[0] : o) : (k[0] < o ? o : k[0]);
+    k[0] = keep_of<Key>(k[0], shfl_xor_key<Key>(k[0], PM), lower, bound);
     return;
   }
   // registers kk and K - 1 - kk trade partners: two at a time, so that only
@@ -319,9 +332,8 @@ template <int K, int SIZE, typename Key> DEVI void mirror_lanes(Key (&k)[K], int
   for (int kk = 0; kk < K / 2; ++kk) {
     const Key oa = shfl_xor_key<Key>(k[K - 1 - kk], PM);
     const Key ob = shfl_xor_key<Key>(k[kk], PM);
-    const Key a = k[kk], b = k[K - 1 - kk];
-    k[kk] = lower ? (a < oa ? a : oa) : (a < oa ? oa : a);
-    k[K - 1 - kk] = lower ? (b < ob ? b : ob) : (b < ob ? ob : b);
+    k[kk] = keep_of<Key>(k[kk], oa, lower, bound);
+    k[K - 1 - kk] = keep_of<Key>(k[K - 1 - kk], ob, lower, bound);
   }
 }
 
