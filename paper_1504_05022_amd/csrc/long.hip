@@ -1831,84 +1831,19 @@ void k_long_w(LongArgs<T> a, int64_t nitems,
   }
 }
 
-// One piece of a split row by one wavefront: the piece's range of every
-// partial, concatenated in segment order, sorted on (column, stream index),
-// folded in that order.  Larger pieces are listed for the work-group kernel.
-template <typename T, int K, typename Key, int MAXS>
-DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T *lds_b,
-                     unsigned int *olist, unsigned int *ocnt) {
+// The gather, sort, fold and output of a piece whose stream (tn entries,
+// at most WAVE * K) the segment table of wave_piece describes: seg_at in
+// lds_a, tbase in lds_b.
+template <typename T, int K, typename Key>
+DEVI void piece_body(LongArgs<T> &a, const int32_t pid, const LongRow &lr, const int32_t lri,
+                     const int32_t c0, const int tn, const int64_t E, const int64_t obase,
+                     unsigned char *lds_a, T *lds_b) {
   constexpr int U = WAVE * K;
   constexpr int LOGU = Log2<U>::v;
   constexpr Key KMAX = KeyMax<Key>::v;
-  static_assert(MAXS <= U, "segment table exceeds the tile buffers");
   const int pos = lane();
-  const int32_t lri = a.piece_lrow[pid];
-  const LongRow lr = a.lrows[lri];
-  if (lr.nseg <= 1) return;
-  const int32_t b = static_cast<int32_t>(pid - lr.piece0);
-  const int32_t c0 = b << lr.shift;
-  const int32_t nseg = lr.nseg;
-  const int32_t *ptab = a.split + lr.sbase;
-  // segment table: lane p holds segments p*KS .. p*KS+KS-1, whose range
-  // bounds are loaded together (one memory round trip); the stream is the
-  // concatenation of the segments' parts of the range, in segment order
-  constexpr int KS = MAXS / WAVE;
-  static_assert(MAXS % WAVE == 0, "segment table rows must fill lanes evenly");
-  const GLOBAL_AS int32_t *lo_row = as_global(ptab + static_cast<int64_t>(b) * nseg);
-  const GLOBAL_AS int32_t *hi_row = as_global(ptab + static_cast<int64_t>(b + 1) * nseg);
-  int32_t slo[KS], slen[KS];
-#pragma unroll
-  for (int j = 0; j < KS; ++j) {
-    const int32_t sg = pos * KS + j;
-    const int32_t sc = sg < nseg ? sg : nseg - 1;
-    slo[j] = lo_row[sc];
-    slen[j] = hi_row[sc];
-  }
-  int32_t tot_len = 0, tot_lo = 0;
-#pragma unroll
-  for (int j = 0; j < KS; ++j) {
-    const bool in = pos * KS + j < nseg;
-    const int32_t lo = in ? max(slo[j], 0) : 0;
-    slen[j] = in ? max(slen[j] - lo, 0) : 0;
-    slo[j] = lo;
-    tot_len += slen[j];
-    tot_lo += lo;
-  }
-  // one scan for both sums (each below 2^31, so the halves never carry):
-  // stream length and this lane's first stream index in the low half, the
-  // sum of the range starts (where this range's output begins) in the high
-  const int64_t packed = (static_cast<int64_t>(tot_lo) << 32) | static_cast<uint32_t>(tot_len);
-  const int64_t incl = group_incl_sum<WAVE>(packed);
-  const int64_t last = group_last<WAVE>(incl);
-  const int64_t E = last & 0xffffffffll;
-  const int64_t obase = last >> 32;
-  if (E > U) {
-    if (pos == 0) olist[atomicAdd(ocnt, 1u)] = static_cast<unsigned int>(pid);
-    return;
-  }
-  const int tn = static_cast<int>(E);
-  // seg_at[t] = segment whose part starts at stream index t (non-empty parts
-  // start at distinct indices), tbase[s] = partial-buffer index of stream
-  // index 0 for segment s; both in the tile buffers, dead before those are
-  // used
-  int32_t *seg_at = reinterpret_cast<int32_t *>(lds_a);
-  int32_t *tbase = reinterpret_cast<int32_t *>(lds_b);
-#pragma unroll
-  for (int kk = 0; kk < K; ++kk) seg_at[pos * K + kk] = -1;
-  wave_sync();
-  {
-    int32_t run = static_cast<int32_t>((incl - packed) & 0xffffffffll);
-#pragma unroll
-    for (int j = 0; j < KS; ++j) {
-      const int32_t sg = pos * KS + j;
-      if (sg < nseg) {
-        tbase[sg] = static_cast<int32_t>(static_cast<int64_t>(sg) * lr.segp + slo[j] - run);
-        if (slen[j] > 0) seg_at[run] = sg;
-      }
-      run += slen[j];
-    }
-  }
-  wave_sync();
+  const int32_t *seg_at = reinterpret_cast<const int32_t *>(lds_a);
+  const int32_t *tbase = reinterpret_cast<const int32_t *>(lds_b);
   const int32_t *pcol = a.pcol + lr.pbase;
   const T *pval = a.pval + lr.pbase;
   // partial-buffer index of every stream entry: the segment is the last one
@@ -1992,6 +1927,96 @@ DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T 
     pc.pad = 0;
     a.pieces[pid] = pc;
   }
+}
+
+// One piece of a split row by one wavefront: the piece's range of every
+// partial, concatenated in segment order, sorted on (column, stream index),
+// folded in that order.  Larger pieces are listed for the work-group kernel.
+template <typename T, int K, typename Key, int MAXS>
+DEVI void wave_piece(LongArgs<T> &a, const int32_t pid, unsigned char *lds_a, T *lds_b,
+                     unsigned int *olist, unsigned int *ocnt) {
+  constexpr int U = WAVE * K;
+  constexpr int LOGU = Log2<U>::v;
+  constexpr Key KMAX = KeyMax<Key>::v;
+  static_assert(MAXS <= U, "segment table exceeds the tile buffers");
+  const int pos = lane();
+  const int32_t lri = a.piece_lrow[pid];
+  const LongRow lr = a.lrows[lri];
+  if (lr.nseg <= 1) return;
+  const int32_t b = static_cast<int32_t>(pid - lr.piece0);
+  const int32_t c0 = b << lr.shift;
+  const int32_t nseg = lr.nseg;
+  const int32_t *ptab = a.split + lr.sbase;
+  // segment table: lane p holds segments p*KS .. p*KS+KS-1, whose range
+  // bounds are loaded together (one memory round trip); the stream is the
+  // concatenation of the segments' parts of the range, in segment order
+  constexpr int KS = MAXS / WAVE;
+  static_assert(MAXS % WAVE == 0, "segment table rows must fill lanes evenly");
+  const GLOBAL_AS int32_t *lo_row = as_global(ptab + static_cast<int64_t>(b) * nseg);
+  const GLOBAL_AS int32_t *hi_row = as_global(ptab + static_cast<int64_t>(b + 1) * nseg);
+  int32_t slo[KS], slen[KS];
+#pragma unroll
+  for (int j = 0; j < KS; ++j) {
+    const int32_t sg = pos * KS + j;
+    const int32_t sc = sg < nseg ? sg : nseg - 1;
+    slo[j] = lo_row[sc];
+    slen[j] = hi_row[sc];
+  }
+  int32_t tot_len = 0, tot_lo = 0;
+#pragma unroll
+  for (int j = 0; j < KS; ++j) {
+    const bool in = pos * KS + j < nseg;
+    const int32_t lo = in ? max(slo[j], 0) : 0;
+    slen[j] = in ? max(slen[j] - lo, 0) : 0;
+    slo[j] = lo;
+    tot_len += slen[j];
+    tot_lo += lo;
+  }
+  // one scan for both sums (each below 2^31, so the halves never carry):
+  // stream length and this lane's first stream index in the low half, the
+  // sum of the range starts (where this range's output begins) in the high
+  const int64_t packed = (static_cast<int64_t>(tot_lo) << 32) | static_cast<uint32_t>(tot_len);
+  const int64_t incl = group_incl_sum<WAVE>(packed);
+  const int64_t last = group_last<WAVE>(incl);
+  const int64_t E = last & 0xffffffffll;
+  const int64_t obase = last >> 32;
+  if (E > U) {
+    if (pos == 0) olist[atomicAdd(ocnt, 1u)] = static_cast<unsigned int>(pid);
+    return;
+  }
+  const int tn = static_cast<int>(E);
+  // seg_at[t] = segment whose part starts at stream index t (non-empty parts
+  // start at distinct indices), tbase[s] = partial-buffer index of stream
+  // index 0 for segment s; both in the tile buffers, dead before those are
+  // used
+  int32_t *seg_at = reinterpret_cast<int32_t *>(lds_a);
+  int32_t *tbase = reinterpret_cast<int32_t *>(lds_b);
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) seg_at[pos * K + kk] = -1;
+  wave_sync();
+  {
+    int32_t run = static_cast<int32_t>((incl - packed) & 0xffffffffll);
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+      const int32_t sg = pos * KS + j;
+      if (sg < nseg) {
+        tbase[sg] = static_cast<int32_t>(static_cast<int64_t>(sg) * lr.segp + slo[j] - run);
+        if (slen[j] > 0) seg_at[run] = sg;
+      }
+      run += slen[j];
+    }
+  }
+  wave_sync();
+  // in the 512-entry pass, a stream that fits half the tile takes the
+  // half-size network (fewer keys per lane to gather, sort and fold); the
+  // 1024-entry pass only receives streams above 512
+  if constexpr (K == 8) {
+    if (tn <= WAVE * (K / 2)) {
+      piece_body<T, K / 2, Key>(a, pid, lr, lri, c0, tn, E, obase, lds_a, lds_b);
+      return;
+    }
+  }
+  piece_body<T, K, Key>(a, pid, lr, lri, c0, tn, E, obase, lds_a, lds_b);
 }
 
 // Every piece (in_list == nullptr), or the listed ones in a grid-stride
