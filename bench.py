@@ -76,6 +76,9 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 4 device-to-device copies of MIB MiB (the calibration "
                          "kernel for the HBM byte counters) and exit")
+    ap.add_argument("--batch-one-shot", action="store_true",
+                    help="only run the one-shot batched product of the 512 banded problems "
+                         "(1 warm-up, 3 timed; the command its kernel profile comes from)")
     ap.add_argument("--diff-forward", action="store_true",
                     help="only run the forward product of the differentiable workload "
                          "(2 warm-up, 3 timed; the command its kernel profiles come from)")
@@ -636,6 +639,33 @@ def diff_forward():
           flush=True)
 
 
+def batch_one_shot():
+    """spgemm_batch_multiply over the 512 banded problems alone."""
+    import torch
+
+    import synthetic as S
+    from paper_1504_05022_amd import lib as L
+
+    L.load()
+    torch.cuda.set_device(0)
+    probs = S.config4()
+    dev = [(L.CsrMatrix.from_host(a), L.CsrMatrix.from_host(b)) for a, b in probs]
+    del probs
+    outs, st = L.batch_multiply(dev, return_stats=True)
+    del outs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        outs = L.batch_multiply(dev)
+        del outs
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / 3
+    print(json.dumps({"workload": "512 banded problems, n log-uniform in [1024, 65536], 4-32 "
+                                  "nnz/row in a 5% band, FP64 even / FP32 odd",
+                      "one_shot_ms": round(ms, 3), "items": st.items, "flops": st.flops}),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -643,6 +673,9 @@ def main():
         return
     if args.diff_forward:
         diff_forward()
+        return
+    if args.batch_one_shot:
+        batch_one_shot()
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
