@@ -1,6 +1,6 @@
 // Expand-sort-compress of up to G*K products per row by an aligned group of
 // G lanes of a wavefront (K products per lane), shared by the per-bin
-// kernels and the batched persistent kernel.  See esc.hip.
+// kernels and the batched per-class kernels.  See esc.hip.
 #pragma once
 
 #include "common.hpp"

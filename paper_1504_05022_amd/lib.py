@@ -386,7 +386,8 @@ def _view(ptr, nbytes, dtype):
 
 
 class Batch:
-    """Many independent products C_p = A_p * B_p in one graph-replayed launch.
+    """Many independent products C_p = A_p * B_p replayed from one HIP graph
+    (one kernel launch per capacity class over the rows of every problem).
 
     ``pairs``: list of (A_p, B_p) CsrMatrix pairs (binary32 and binary64 may
     be mixed).  The matrices must stay alive and keep their patterns.
