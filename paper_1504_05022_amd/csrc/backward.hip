@@ -57,9 +57,13 @@ __global__ __launch_bounds__(256) void k_grad_b(const int64_t *tptr, const int32
 // product a_ij dC_ik of the dB sums; k_grad_b_sum adds them per b_jk over
 // A's transposed pattern (ascending i).  Sums, products and their order are
 // those of the definition (and of k_grad_b).
-constexpr int BW_CH = 1024;
-constexpr int BW_NT = 256;
+constexpr int BW_CH = 512;
+constexpr int BW_NT = 128;  // two wavefronts: 32 KB of dense rows per work-group
 constexpr int BW_U = 8;  // entries of b_j* whose loads are in flight together
+// with the dense dC row (16 KB of LDS per wavefront, so LDS, not registers,
+// caps the kernel at two wavefronts per SIMD) a whole block of 32 entries
+// of b_j* is loaded at once: fewer dependent round trips per entry
+constexpr int BW_UD = 32;
 constexpr int BW_MAP_BYTES = 16384;  // dense dC row per wavefront
 
 template <typename T> constexpr int bw_map_cols() { return BW_MAP_BYTES / static_cast<int>(sizeof(T)); }
@@ -107,19 +111,20 @@ __global__ __launch_bounds__(BW_NT) void k_grad_entries(
       T *wp = W ? W + (P[ee] - q0) : nullptr;
       T s = T(0);
       int32_t from = c0;
-      // blocks of BW_U entries of b_j*: their loads are issued together
+      // blocks of UB entries of b_j*: their loads are issued together
       // (clamped to the row), then the block is added in order
-      for (int32_t qb = q0; qb < q1; qb += BW_U) {
-        int32_t kk[BW_U];
-        T bv[BW_U];
+      constexpr int UB = DENSE ? BW_UD : BW_U;
+      for (int32_t qb = q0; qb < q1; qb += UB) {
+        int32_t kk[UB];
+        T bv[UB];
 #pragma unroll
-        for (int u = 0; u < BW_U; ++u) {
+        for (int u = 0; u < UB; ++u) {
           const int32_t q = qb + u < q1 ? qb + u : q1 - 1;
           kk[u] = bcol[q];
           bv[u] = bval[q];
         }
 #pragma unroll
-        for (int u = 0; u < BW_U; ++u) {
+        for (int u = 0; u < UB; ++u) {
           if (qb + u < q1) {
             T y;
             if (DENSE) {
