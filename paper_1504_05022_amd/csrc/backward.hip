@@ -151,15 +151,19 @@ __global__ __launch_bounds__(BW_NT) void k_grad_entries(
 }
 
 // dB_jk = sum over A's column j (ascending i) of the products a_ij dC_ik in W.
+// BW_SUB lanes per row of B (each lane sums its own entries, so rows share
+// a wavefront without any ordering between them).
+constexpr int BW_SUB = 32;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_grad_b_sum(const int64_t *tptr, const int32_t *tpos,
                                                     const int64_t *P, const int32_t *brp,
                                                     int64_t kb, const T *W, T *dB) {
-  const int64_t j = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t j = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / BW_SUB;
   if (j >= kb) return;
   const int64_t t0 = tptr[j], t1 = tptr[j + 1];
   const int32_t q0 = brp[j], q1 = brp[j + 1];
-  for (int32_t q = q0 + lane(); q < q1; q += WAVE) {
+  for (int32_t q = q0 + (lane() & (BW_SUB - 1)); q < q1; q += BW_SUB) {
     T s = T(0);
     // blocks of BW_U entries of A's column j: offsets, then products, each
     // loaded together (clamped to the column), then added in order
@@ -198,7 +202,7 @@ template <typename T>
 void launch_grad_b_sum(const int64_t *tptr, const int32_t *tpos, const int64_t *P,
                        const int32_t *brp, int64_t kb, const T *W, T *dB, hipStream_t s) {
   if (kb <= 0) return;
-  hipLaunchKernelGGL((k_grad_b_sum<T>), dim3((kb * WAVE + 255) / 256), dim3(256), 0, s, tptr,
+  hipLaunchKernelGGL((k_grad_b_sum<T>), dim3((kb * BW_SUB + 255) / 256), dim3(256), 0, s, tptr,
                      tpos, P, brp, kb, W, dB);
 }
 
