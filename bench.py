@@ -79,6 +79,10 @@ def parse():
     ap.add_argument("--batch-one-shot", action="store_true",
                     help="only run the one-shot batched product of the 512 banded problems "
                          "(1 warm-up, 3 timed; the command its kernel profile comes from)")
+    ap.add_argument("--diff-backward", action="store_true",
+                    help="only run the backward of the differentiable workload (plan and "
+                         "forward once, then 1 warm-up and 3 timed backward calls; the command "
+                         "its kernel profile comes from)")
     ap.add_argument("--diff-forward", action="store_true",
                     help="only run the forward product of the differentiable workload "
                          "(2 warm-up, 3 timed; the command its kernel profiles come from)")
@@ -639,6 +643,38 @@ def diff_forward():
           flush=True)
 
 
+def diff_backward():
+    """The differentiable workload's backward alone: dA and dB of a random
+    dC on the forward's pattern (A 500000^2 power law x B 500000x4096,
+    binary32)."""
+    import torch
+
+    import synthetic as S
+    from paper_1504_05022_amd import lib as L
+
+    L.load()
+    torch.cuda.set_device(0)
+    A, B = S.config5()
+    dA, dB = L.CsrMatrix.from_host(A), L.CsrMatrix.from_host(B)
+    del A, B
+    plan = L.Plan(dA, dB)
+    C = plan.compute()
+    g = torch.Generator(device="cuda").manual_seed(5)
+    dc = torch.randn(C.nnz, generator=g, dtype=torch.float32, device="cuda")
+    plan.backward(C, dc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        plan.backward(C, dc)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / 3
+    fl = int(plan.info.flops)
+    plan.close()
+    print(json.dumps({"workload": "A 500000^2 power law (2.2, mean 20) x B 500000x4096 (32/row), "
+                                  "FP32", "backward_ms": round(ms, 3),
+                      "backward_gflops": round(2 * fl / (ms * 1e-3) / 1e9, 2)}), flush=True)
+
+
 def batch_one_shot():
     """spgemm_batch_multiply over the 512 banded problems alone."""
     import torch
@@ -676,6 +712,9 @@ def main():
         return
     if args.batch_one_shot:
         batch_one_shot()
+        return
+    if args.diff_backward:
+        diff_backward()
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
