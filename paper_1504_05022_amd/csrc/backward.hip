@@ -81,11 +81,10 @@ __global__ __launch_bounds__(BW_NT) void k_grad_entries(
   const int64_t e0 = (static_cast<int64_t>(blockIdx.x) * NWV + w) * BW_CH;
   if (e0 >= nnz) return;  // uniform across the wavefront; no work-group barriers here
   const int64_t e1 = e0 + BW_CH < nnz ? e0 + BW_CH : nnz;
+  // dense dC row: every column a row looks up is one of its own C columns
+  // (C holds every structural product), written by that row's scatter, so
+  // the map is never cleared
   T *mp = map + w * MAPC;
-  if (DENSE) {
-    for (int x = ln; x < MAPC; x += WAVE) mp[x] = T(0);
-    wave_sync();
-  }
   int64_t lo = 0, hi = m;  // the row holding e0: last i with arp[i] <= e0
   while (hi - lo > 1) {
     const int64_t mid = (lo + hi) >> 1;
@@ -141,11 +140,7 @@ __global__ __launch_bounds__(BW_NT) void k_grad_entries(
       }
       if (dA) dA[ee] = s;
     }
-    if (DENSE) {
-      wave_sync();
-      for (int32_t x = c0 + ln; x < c1; x += WAVE) mp[ccol[x]] = T(0);
-      wave_sync();
-    }
+    if (DENSE) wave_sync();  // this row's lookups precede the next row's scatter
     e = re;
   }
 }
