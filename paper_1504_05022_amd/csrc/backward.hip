@@ -225,18 +225,48 @@ __global__ void k_col_count(const int32_t *acol, int64_t nnz, int32_t *cnt) {
 }
 
 // Scatter (row, position) of every entry into its column's segment, in any
-// order; k_col_sort restores ascending rows.
+// order; k_col_sort restores ascending rows.  One wavefront per chunk of
+// TS_CH consecutive entries (rows found by one binary search per wavefront,
+// then walked per lane), TS_U entries per lane whose column loads and slot
+// atomics are in flight together.
+constexpr int TS_U = 4;
+constexpr int TS_CH = WAVE * TS_U;
+
 __global__ __launch_bounds__(256) void k_col_scatter(const int32_t *arp, const int32_t *acol,
-                                                     int64_t m, const int64_t *tptr,
+                                                     int64_t m, int64_t nnz, const int64_t *tptr,
                                                      int32_t *fill, int32_t *trow,
                                                      int32_t *tpos) {
-  const int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE;
-  if (i >= m) return;
-  for (int32_t e = arp[i] + lane(); e < arp[i + 1]; e += WAVE) {
-    const int32_t j = acol[e];
-    const int32_t slot = atomicAdd(&fill[j], 1);
-    trow[tptr[j] + slot] = static_cast<int32_t>(i);
-    tpos[tptr[j] + slot] = e;
+  const int64_t e0 = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE * TS_CH;
+  if (e0 >= nnz) return;  // uniform across the wavefront
+  int64_t lo = 0, hi = m;  // the row holding e0: last i with arp[i] <= e0
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (arp[mid] <= e0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  int64_t e[TS_U], row[TS_U];
+  int32_t col[TS_U], slot[TS_U];
+  int64_t i = lo;
+#pragma unroll
+  for (int u = 0; u < TS_U; ++u) {
+    e[u] = e0 + u * WAVE + lane();
+    if (e[u] < nnz)
+      while (arp[i + 1] <= e[u]) ++i;  // entries ascend with u, so rows do too
+    row[u] = i;
+  }
+#pragma unroll
+  for (int u = 0; u < TS_U; ++u) col[u] = e[u] < nnz ? acol[e[u]] : 0;
+#pragma unroll
+  for (int u = 0; u < TS_U; ++u) slot[u] = e[u] < nnz ? atomicAdd(&fill[col[u]], 1) : 0;
+#pragma unroll
+  for (int u = 0; u < TS_U; ++u) {
+    if (e[u] < nnz) {
+      const int64_t d = tptr[col[u]] + slot[u];
+      trow[d] = static_cast<int32_t>(row[u]);
+      tpos[d] = static_cast<int32_t>(e[u]);
+    }
   }
 }
 
@@ -266,9 +296,11 @@ void launch_transpose_pattern(const int32_t *arp, const int32_t *acol, int64_t m
     hipLaunchKernelGGL(k_col_count, dim3((nnz + 255) / 256), dim3(256), 0, s, acol, nnz, cnt);
   scan_i32(cnt, k, tptr, part, s);
   launch_zero(cnt, static_cast<size_t>(k) * 4, s);
-  if (m > 0)
-    hipLaunchKernelGGL(k_col_scatter, dim3((m * WAVE + 255) / 256), dim3(256), 0, s, arp, acol,
-                       m, tptr, cnt, trow, tpos);
+  if (nnz > 0) {
+    const int64_t waves = (nnz + TS_CH - 1) / TS_CH;
+    hipLaunchKernelGGL(k_col_scatter, dim3((waves * WAVE + 255) / 256), dim3(256), 0, s, arp,
+                       acol, m, nnz, tptr, cnt, trow, tpos);
+  }
   if (k > 0)
     hipLaunchKernelGGL(k_col_sort, dim3((k + 255) / 256), dim3(256), 0, s, tptr, k, trow, tpos);
 }
