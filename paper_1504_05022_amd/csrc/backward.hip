@@ -64,6 +64,7 @@ constexpr int BW_U = 8;  // entries of b_j* whose loads are in flight together
 // caps the kernel at two wavefronts per SIMD) a whole block of 32 entries
 // of b_j* is loaded at once: fewer dependent round trips per entry
 constexpr int BW_UD = 32;
+constexpr int BW_SC = 8;  // passes of a dC row's scatter whose loads are in flight together
 constexpr int BW_MAP_BYTES = 16384;  // dense dC row per wavefront
 
 template <typename T> constexpr int bw_map_cols() { return BW_MAP_BYTES / static_cast<int>(sizeof(T)); }
@@ -100,7 +101,22 @@ __global__ __launch_bounds__(BW_NT) void k_grad_entries(
     const int64_t re = arp[i + 1] < e1 ? static_cast<int64_t>(arp[i + 1]) : e1;
     const int32_t c0 = crp[i], c1 = crp[i + 1];
     if (DENSE) {
-      for (int32_t x = c0 + ln; x < c1; x += WAVE) mp[ccol[x]] = dc[x];
+      // the row's dC entries, BW_SC passes of the wavefront loaded together
+      // (clamped to the row) before they are written to the map
+      for (int32_t xb = c0; xb < c1; xb += BW_SC * WAVE) {
+        int32_t cc[BW_SC];
+        T vv[BW_SC];
+#pragma unroll
+        for (int u = 0; u < BW_SC; ++u) {
+          const int32_t x = xb + u * WAVE + ln;
+          const int32_t xc = x < c1 ? x : c1 - 1;
+          cc[u] = ccol[xc];
+          vv[u] = dc[xc];
+        }
+#pragma unroll
+        for (int u = 0; u < BW_SC; ++u)
+          if (xb + u * WAVE + ln < c1) mp[cc[u]] = vv[u];
+      }
       wave_sync();
     }
     for (int64_t ee = e + ln; ee < re; ee += WAVE) {
